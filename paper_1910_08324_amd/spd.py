@@ -1,0 +1,273 @@
+"""Python binding of libspd (include/spd.h): argument marshalling only.
+
+Every step of the search runs in the library's gfx950 kernels; PyTorch supplies device memory
+and the current HIP stream.  There is no CPU fallback: if libspd.so is missing, or no ROCm
+device is present, the calls below raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libspd.so")
+
+SPD_OK, SPD_EINVAL, SPD_EALIGN, SPD_EWORKSPACE, SPD_EHIP = 0, -1, -2, -3, -4
+EXHAUSTIVE, BOXDIT, IGRID = 0, 1, 2
+WRITE_PLANES, WRITE_CANDIDATES = 1, 2
+MAX_LEVELS = 24
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int32),
+        ("l_end", ctypes.c_int32),
+        ("widths", ctypes.POINTER(ctypes.c_int32)),
+        ("n_widths", ctypes.c_int32),
+        ("boxdit_lmax", ctypes.POINTER(ctypes.c_int32)),
+        ("n_boxdit_lmax", ctypes.c_int32),
+        ("igrid_depth", ctypes.c_int32),
+        ("igrid_layers", ctypes.c_int32),
+        ("threshold", ctypes.c_float),
+        ("flags", ctypes.c_uint32),
+        ("segment", ctypes.c_int32),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_levels", ctypes.c_int32),
+        ("top_level", ctypes.c_int32),
+        ("max_width", ctypes.c_int32),
+        ("required_halo", ctypes.c_int32),
+        ("level_shift", ctypes.c_int32 * MAX_LEVELS),
+        ("level_nwidths", ctypes.c_int32 * MAX_LEVELS),
+        ("plane_offset", ctypes.c_int64 * MAX_LEVELS),
+        ("plane_slots", ctypes.c_int64 * MAX_LEVELS),
+        ("plane_pitch", ctypes.c_int64 * MAX_LEVELS),
+        ("plane_elems", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_int64),
+        ("segment", ctypes.c_int32),
+        ("n_segments", ctypes.c_int32),
+    ]
+
+
+CANDIDATE_DTYPE = np.dtype([("start", "<i8"), ("dm", "<i4"), ("width", "<i4"), ("level", "<i4"),
+                            ("snr", "<f4")])
+assert CANDIDATE_DTYPE.itemsize == 24
+
+_lib = None
+
+
+def load():
+    """Load libspd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1910_08324_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        lib.spd_plan.argtypes = [ctypes.POINTER(Params), i32, i32, i32, ctypes.POINTER(PlanInfo)]
+        lib.spd_plan.restype = ctypes.c_int
+        lib.spd_level_widths.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(i32), i32,
+                                         ctypes.POINTER(i32)]
+        lib.spd_level_widths.restype = ctypes.c_int
+        lib.spd_search.argtypes = [ctypes.POINTER(Params), P, i64, i32, i32, i32, i64, P, P, P, P,
+                                   P, i64, P, P, i64, P]
+        lib.spd_search.restype = ctypes.c_int
+        lib.spd_error_string.argtypes = [ctypes.c_int]
+        lib.spd_error_string.restype = ctypes.c_char_p
+        lib.spd_abi_version.argtypes = []
+        lib.spd_abi_version.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+class SpdError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {load().spd_error_string(status).decode()} ({status})")
+
+
+def _check(status: int, what: str):
+    if status != SPD_OK:
+        raise SpdError(status, what)
+
+
+@dataclasses.dataclass
+class Config:
+    """A search configuration.  `method` names: 'exh', 'bd<L>' (BoxDIT, L^i_max = L), 'ig<d>'
+    (IGRID depth d, 2^(d+1) layers), 'dit' (IGRID depth 0, one layer)."""
+
+    method: str
+    l_end: int
+    threshold: float = 5.0
+    planes: bool = True
+    candidates: bool = True
+    widths: Optional[Sequence[int]] = None          # exhaustive: explicit width list
+    boxdit_lmax: Optional[Sequence[int]] = None     # BoxDIT: per-iteration L^i_max
+    igrid_depth: Optional[int] = None
+    igrid_layers: int = 0
+    segment: int = 0
+
+    def params(self) -> Tuple[Params, list]:
+        keep = []
+        p = Params()
+        m = self.method.lower()
+        p.l_end = int(self.l_end)
+        p.threshold = float(self.threshold)
+        p.flags = (WRITE_PLANES if self.planes else 0) | (WRITE_CANDIDATES if self.candidates else 0)
+        p.segment = int(self.segment)
+        if m in ("exh", "exhaustive"):
+            p.method = EXHAUSTIVE
+            if self.widths is not None:
+                arr = (ctypes.c_int32 * len(self.widths))(*[int(w) for w in self.widths])
+                keep.append(arr)
+                p.widths = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+                p.n_widths = len(self.widths)
+        elif m.startswith("bd"):
+            p.method = BOXDIT
+            lm = list(self.boxdit_lmax) if self.boxdit_lmax is not None else [int(m[2:].lstrip("-"))]
+            arr = (ctypes.c_int32 * len(lm))(*lm)
+            keep.append(arr)
+            p.boxdit_lmax = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+            p.n_boxdit_lmax = len(lm)
+        elif m.startswith("ig") or m == "dit":
+            p.method = IGRID
+            if m == "dit":
+                p.igrid_depth, p.igrid_layers = 0, 1
+            else:
+                p.igrid_depth = int(self.igrid_depth if self.igrid_depth is not None
+                                    else m[2:].strip("()"))
+                p.igrid_layers = int(self.igrid_layers)
+        else:
+            raise ValueError(f"unknown method {self.method!r}")
+        return p, keep
+
+
+def plan(cfg: Config, n_dm: int, n_in: int, n_out: Optional[int] = None) -> PlanInfo:
+    p, keep = cfg.params()
+    info = PlanInfo()
+    _check(load().spd_plan(ctypes.byref(p), n_dm, n_in, n_in if n_out is None else n_out,
+                           ctypes.byref(info)), "spd_plan")
+    return info
+
+
+def level_widths(cfg: Config) -> List[List[int]]:
+    p, keep = cfg.params()
+    lib = load()
+    out = []
+    n = ctypes.c_int32()
+    for lev in range(MAX_LEVELS):
+        st = lib.spd_level_widths(ctypes.byref(p), lev, None, 0, ctypes.byref(n))
+        if st == SPD_EINVAL and lev > 0:
+            break
+        _check(st, "spd_level_widths")
+        buf = (ctypes.c_int32 * n.value)()
+        _check(lib.spd_level_widths(ctypes.byref(p), lev, buf, n.value, ctypes.byref(n)),
+               "spd_level_widths")
+        out.append(list(buf))
+    return out
+
+
+@dataclasses.dataclass
+class Result:
+    info: PlanInfo
+    snr: Optional["torch.Tensor"]          # flat float32 planes (device)
+    width: Optional["torch.Tensor"]        # flat uint16 planes stored as int16 (device)
+    cand: Optional["torch.Tensor"]         # raw candidate bytes (device)
+    count: Optional["torch.Tensor"]        # int64[1] total candidates (device)
+    n_dm: int
+
+    def level(self, i: int):
+        """(Y, W) device views of level i, shape (n_dm, slots)."""
+        off = int(self.info.plane_offset[i])
+        pitch = int(self.info.plane_pitch[i])
+        slots = int(self.info.plane_slots[i])
+        Y = self.snr[off: off + self.n_dm * pitch].view(self.n_dm, pitch)[:, :slots]
+        W = self.width[off: off + self.n_dm * pitch].view(self.n_dm, pitch)[:, :slots]
+        return Y, W
+
+    def planes_host(self):
+        """[{'k', 'Y' float32, 'W' int64}] per level, copied to the host."""
+        out = []
+        for i in range(self.info.n_levels):
+            Y, W = self.level(i)
+            out.append({"k": int(self.info.level_shift[i]), "Y": Y.cpu().numpy(),
+                        "W": W.cpu().numpy().view(np.uint16).astype(np.int64)})
+        return out
+
+    def candidates_host(self) -> np.ndarray:
+        total = int(self.count.cpu().item())
+        n = min(total, self.cand.numel() // CANDIDATE_DTYPE.itemsize)
+        raw = self.cand[: n * CANDIDATE_DTYPE.itemsize].cpu().numpy()
+        return raw.view(CANDIDATE_DTYPE)
+
+
+def search(x, mean, sigma, cfg: Config, n_in: Optional[int] = None, n_out: Optional[int] = None,
+           t0: int = 0, cand_cap: int = 1 << 20, workspace=None, out: Optional[Result] = None,
+           stream=None) -> Result:
+    """Run the search on device tensors x [n_dm, ld] float32, mean/sigma [n_dm] float32.
+
+    Output buffers are allocated with torch unless `out` (a previous Result of the same shape)
+    is given; the workspace likewise.  Asynchronous on the current stream."""
+    import torch
+
+    if not (x.is_cuda and mean.is_cuda and sigma.is_cuda):
+        raise ValueError("x, mean and sigma must be device tensors")
+    if x.dtype != torch.float32 or mean.dtype != torch.float32 or sigma.dtype != torch.float32:
+        raise ValueError("x, mean and sigma must be float32")
+    if x.dim() != 2 or x.stride(1) != 1:
+        raise ValueError("x must be 2-D with unit stride along time")
+    n_dm, n = x.shape
+    n_in = n if n_in is None else int(n_in)
+    n_out = n_in if n_out is None else int(n_out)
+    if mean.numel() != n_dm or sigma.numel() != n_dm:
+        raise ValueError("mean and sigma need one value per row")
+    p, keep = cfg.params()
+    info = PlanInfo()
+    lib = load()
+    _check(lib.spd_plan(ctypes.byref(p), n_dm, n_in, n_out, ctypes.byref(info)), "spd_plan")
+    dev = x.device
+    if out is None:
+        snr = width = cand = count = None
+        if cfg.planes:
+            snr = torch.empty(int(info.plane_elems), dtype=torch.float32, device=dev)
+            width = torch.empty(int(info.plane_elems), dtype=torch.int16, device=dev)
+        if cfg.candidates:
+            cand = torch.empty(max(1, cand_cap) * CANDIDATE_DTYPE.itemsize, dtype=torch.uint8,
+                               device=dev)
+            count = torch.zeros(1, dtype=torch.int64, device=dev)
+        out = Result(info, snr, width, cand, count, n_dm)
+    else:
+        out.info = info
+        if cfg.planes and (out.snr is None or out.snr.numel() < info.plane_elems):
+            raise ValueError("`out` planes are too small for this search")
+    if cfg.candidates:
+        cap = out.cand.numel() // CANDIDATE_DTYPE.itemsize
+    else:
+        cap = 0
+    if workspace is None:
+        workspace = torch.empty(max(256, int(info.workspace_bytes)), dtype=torch.uint8, device=dev)
+    elif workspace.numel() < info.workspace_bytes:
+        raise ValueError("workspace too small")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def ptr(t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    st = lib.spd_search(ctypes.byref(p), ptr(x), x.stride(0), n_dm, n_in, n_out, int(t0),
+                        ptr(mean), ptr(sigma), ptr(out.snr) if cfg.planes else None,
+                        ptr(out.width) if cfg.planes else None,
+                        ptr(out.cand) if cfg.candidates else None, cap,
+                        ptr(out.count) if cfg.candidates else None, ptr(workspace),
+                        workspace.numel(), ctypes.c_void_p(stream))
+    _check(st, "spd_search")
+    out._workspace = workspace
+    return out

@@ -20,6 +20,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import Iterable, List, Optional, Sequence
 
 import numpy as np
@@ -44,13 +46,24 @@ class Pulse:
 
 
 def noise_rows(n: int, seed: int, rows: Iterable[int], sigma: float = 1.0,
-               mu: float = 0.0) -> np.ndarray:
-    """White noise N(mu, sigma^2), float32, one independent PCG64 stream per row."""
+               mu: float = 0.0, threads: Optional[int] = None) -> np.ndarray:
+    """White noise N(mu, sigma^2), float32, one independent PCG64 stream per row (rows are
+    filled in parallel threads; the result does not depend on the thread count)."""
     rows = list(rows)
     out = np.empty((len(rows), n), dtype=np.float32)
-    for i, d in enumerate(rows):
-        rng = np.random.Generator(np.random.PCG64([int(seed), int(d)]))
+
+    def fill(i: int) -> None:
+        rng = np.random.Generator(np.random.PCG64([int(seed), int(rows[i])]))
         rng.standard_normal(n, dtype=np.float32, out=out[i])
+
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    if len(rows) * n >= (1 << 22) and threads > 1:
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(fill, range(len(rows))))
+    else:
+        for i in range(len(rows)):
+            fill(i)
     if sigma != 1.0:
         out *= np.float32(sigma)
     if mu != 0.0:

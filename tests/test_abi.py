@@ -1,0 +1,136 @@
+"""Host-side checks of the C ABI (no GPU needed): exported symbols, level tables against the
+oracle's width sets, output geometry and argument errors."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import widths as ow
+from paper_1910_08324_amd import spd
+from tests.conftest import ROOT
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(spd.LIB_PATH):
+        from paper_1910_08324_amd import build
+        build.build()
+    return spd.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    hdr = open(os.path.join(ROOT, "include", "spd.h")).read()
+    names = re.findall(r"^\w[\w\s\*]*?\b(spd_\w+)\s*\(", hdr, flags=re.M)
+    assert set(names) >= {"spd_plan", "spd_level_widths", "spd_search", "spd_error_string",
+                          "spd_abi_version"}
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.spd_abi_version() == 1
+
+
+CASES = [("exh", 1), ("exh", 256), ("exh", 8192), ("dit", 8192)] + \
+    [(m, L) for m in ("ig1", "ig2", "ig3", "bd8", "bd16", "bd32")
+     for L in (1, 2, 3, 7, 64, 100, 256, 1000, 4096, 8000, 8192, 65535)]
+
+
+@pytest.mark.parametrize("method,l_end", CASES)
+def test_level_widths_match_oracle(lib, method, l_end):
+    got = spd.level_widths(spd.Config(method, l_end))
+    ref = ow.method_levels(method, l_end)
+    assert got == [w for _, w in ref]
+    info = spd.plan(spd.Config(method, l_end), 3, 100000)
+    assert info.n_levels == len(ref)
+    assert [info.level_shift[i] for i in range(info.n_levels)] == [k for k, _ in ref]
+    assert info.max_width == max(w for _, ws in ref for w in ws)
+
+
+def test_level_widths_more_variants(lib):
+    for d in range(0, 5):
+        for P in (1, 2, 4, 8, 16, 32):
+            if P < 2 ** d:
+                continue
+            cfg = spd.Config("ig", 5000, igrid_depth=d, igrid_layers=P)
+            try:
+                got = spd.level_widths(cfg)
+            except spd.SpdError:
+                assert len(ow.igrid_levels(d, 5000, layers=P)[0][1]) > 64
+                continue
+            assert got == [w for _, w in ow.igrid_levels(d, 5000, layers=P)]
+    cfg = spd.Config("bd", 3000, boxdit_lmax=[16, 8, 4, 32])
+    assert spd.level_widths(cfg) == [w for _, w in ow.boxdit_levels([16, 8, 4, 32], 3000)]
+    cfg = spd.Config("exh", 50, widths=[1, 3, 9, 50])
+    assert spd.level_widths(cfg) == [[1, 3, 9, 50]]
+
+
+def test_plan_geometry(lib):
+    info = spd.plan(spd.Config("ig1", 8192), 4096, 262144)
+    assert info.n_levels == 12 and info.top_level == 11 and info.required_halo == 8191
+    off = 0
+    for i in range(info.n_levels):
+        slots = -(-262144 // (1 << info.level_shift[i]))
+        assert info.plane_slots[i] == slots
+        assert info.plane_pitch[i] % 64 == 0 and info.plane_pitch[i] >= slots
+        assert info.plane_offset[i] == off
+        off += info.plane_pitch[i] * 4096
+    assert info.plane_elems == off
+    assert info.workspace_bytes > 0 and info.workspace_bytes % 256 == 0
+    assert info.segment * info.n_segments >= 262144
+    ragged = spd.plan(spd.Config("bd16", 300), 5, 1001, 999)
+    assert [ragged.plane_slots[i] for i in range(ragged.n_levels)] == \
+        [-(-999 // (1 << ragged.level_shift[i])) for i in range(ragged.n_levels)]
+
+
+@pytest.mark.parametrize("cfg,dims", [
+    (spd.Config("bd7", 100), (1, 10, 10)),                       # odd L_max
+    (spd.Config("bd", 100, boxdit_lmax=[8, 3]), (1, 10, 10)),
+    (spd.Config("bd", 100, boxdit_lmax=[66]), (1, 10, 10)),      # too many widths per level
+    (spd.Config("ig5", 100), (1, 10, 10)),                      # depth out of range
+    (spd.Config("ig", 100, igrid_depth=2, igrid_layers=2), (1, 10, 10)),
+    (spd.Config("ig", 100, igrid_depth=1, igrid_layers=6), (1, 10, 10)),
+    (spd.Config("exh", 0), (1, 10, 10)),
+    (spd.Config("exh", 70000), (1, 10, 10)),
+    (spd.Config("exh", 10, widths=[2, 2]), (1, 10, 10)),
+    (spd.Config("exh", 10, widths=[11]), (1, 10, 10)),
+    (spd.Config("exh", 20000, widths=[1, 2]), (1, 10, 10)),      # list mode capped at 16384
+    (spd.Config("exh", 10, planes=False, candidates=False), (1, 10, 10)),
+    (spd.Config("exh", 10, segment=512), (1, 10, 10)),
+    (spd.Config("ig1", 64, segment=1000), (1, 10, 10)),
+    (spd.Config("ig1", 64), (1, 10, 11)),                       # n_out > n_in
+    (spd.Config("ig1", 64), (0, 10, 10)),
+    (spd.Config("ig1", 64), (1, 0, 0)),
+])
+def test_plan_rejects(lib, cfg, dims):
+    with pytest.raises(spd.SpdError) as e:
+        spd.plan(cfg, *dims)
+    assert e.value.status == spd.SPD_EINVAL
+
+
+def _search_raw(lib, cfg, x=1 << 20, t0=0, ws=None, wsb=None, planes=(1 << 21, 1 << 22),
+                cand=1 << 23, count=1 << 24, n=(4, 4096, 4096)):
+    p, keep = cfg.params()
+    info = spd.PlanInfo()
+    ok = lib.spd_plan(ctypes.byref(p), n[0], n[1], n[2], ctypes.byref(info)) == 0
+    wsb = (info.workspace_bytes if ok else 1 << 30) if wsb is None else wsb
+    ws = (1 << 30) if ws is None else ws
+    V = ctypes.c_void_p
+    return lib.spd_search(ctypes.byref(p), V(x) if x else None, n[1], n[0], n[1], n[2], t0,
+                          V(1 << 25), V(1 << 26), V(planes[0]) if planes[0] else None,
+                          V(planes[1]) if planes[1] else None, V(cand) if cand else None, 16,
+                          V(count) if count else None, V(ws) if ws else None, wsb, None)
+
+
+def test_search_argument_errors_before_any_launch(lib):
+    """Every argument error is reported synchronously, before anything is enqueued (the fake
+    device addresses below are never dereferenced)."""
+    cfg = spd.Config("ig1", 64)
+    assert _search_raw(lib, cfg, x=0) == spd.SPD_EINVAL
+    assert _search_raw(lib, cfg, planes=(0, 0)) == spd.SPD_EINVAL
+    assert _search_raw(lib, cfg, count=0) == spd.SPD_EINVAL
+    assert _search_raw(lib, cfg, t0=3) == spd.SPD_EALIGN          # K = 4: t0 % 16 != 0
+    assert _search_raw(lib, cfg, ws=0) == spd.SPD_EWORKSPACE
+    info = spd.plan(cfg, 4, 4096)
+    assert _search_raw(lib, cfg, wsb=info.workspace_bytes - 1) == spd.SPD_EWORKSPACE
+    assert _search_raw(lib, cfg, ws=(1 << 30) + 8) == spd.SPD_EALIGN
+    assert _search_raw(lib, spd.Config("bd5", 64)) == spd.SPD_EINVAL
+    assert b"t0" in lib.spd_error_string(spd.SPD_EALIGN)
