@@ -79,8 +79,8 @@ extern "C" {
  *   threshold       candidates need SNR strictly above it.
  *   flags           SPD_WRITE_PLANES | SPD_WRITE_CANDIDATES.
  *   segment         samples per work item along time (0 = chosen by the library).  Results do not
- *                   depend on it; a nonzero value must be a multiple of 4096 (lossy) or 256
- *                   (exhaustive) and of 2^(K+2).
+ *                   depend on it.  BoxDIT / IGRID: a multiple of 1024 and of 2^(K+2);
+ *                   exhaustive: 256 only.
  */
 typedef struct {
     int32_t method;
@@ -162,6 +162,27 @@ int spd_search(const spd_params *params, const float *x, int64_t ld, int32_t n_d
                int32_t n_out, int64_t t0, const float *mean, const float *sigma, float *snr,
                uint16_t *width, spd_candidate *cand, int64_t cand_cap, int64_t *cand_count,
                void *workspace, int64_t workspace_bytes, void *hip_stream);
+
+/*
+ * The two stages of spd_search as separate calls, for callers that time or overlap them.
+ * spd_search == spd_filter followed by spd_peaks on the same stream, parameters, sizes,
+ * planes and workspace.
+ *
+ * spd_filter: the boxcar search only (Sections 3.1 and 3.2): writes the planes (to snr/width,
+ *   or into the workspace when SPD_WRITE_PLANES is not set) and, when SPD_WRITE_CANDIDATES is
+ *   set, records in the workspace the slots above the threshold for spd_peaks.  For BoxDIT and
+ *   IGRID it is a single kernel launch.  Arguments as for spd_search.
+ * spd_peaks: candidate selection from the planes and records left by spd_filter (params->flags
+ *   must include SPD_WRITE_CANDIDATES; snr/width as given to spd_filter).  Arguments as for
+ *   spd_search.
+ */
+int spd_filter(const spd_params *params, const float *x, int64_t ld, int32_t n_dm, int32_t n_in,
+               int32_t n_out, const float *mean, const float *sigma, float *snr, uint16_t *width,
+               void *workspace, int64_t workspace_bytes, void *hip_stream);
+
+int spd_peaks(const spd_params *params, int32_t n_dm, int32_t n_in, int32_t n_out, int64_t t0,
+              const float *snr, const uint16_t *width, spd_candidate *cand, int64_t cand_cap,
+              int64_t *cand_count, void *workspace, int64_t workspace_bytes, void *hip_stream);
 
 /* Human-readable text for a status code (static storage; includes the last HIP error text for
  * SPD_EHIP on this thread). */

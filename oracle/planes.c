@@ -19,6 +19,19 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the oracle's parallel loops use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 static void one_slot(const double *P, int64_t s, int32_t n_in, double sigma,
                      const int32_t *w, int32_t nw, double *Y, int32_t *W, double *gap)

@@ -44,6 +44,8 @@ def _load():
         lib.oracle_points.restype = None
         lib.oracle_snr.argtypes = [P, i64, i32, P, P, i64, P, P, P, P]
         lib.oracle_snr.restype = None
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -129,3 +131,8 @@ def snr(x: np.ndarray, mean, sigma, rows, starts, widths, n_in: int | None = Non
     _load().oracle_snr(_ptr(x), ld, n_in, _ptr(mean), _ptr(sigma), len(rows), _ptr(rows),
                        _ptr(starts), _ptr(widths), _ptr(out))
     return out
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_load().oracle_threads())

@@ -159,7 +159,7 @@ struct Layout {
     spd_plan_info info;
     int seg = 0, n_seg = 0, max_chunks = 0, lds_bytes = 0;
     int64_t n_slabs = 0, slabs_per_wave = 0;
-    int n_waves = 0, slab_cap = 0, n_scale = 0;
+    int n_waves = 0, slab_cap = 0, n_scale = 0, lds_scale = 0;
     int64_t off_scale = 0, off_mask = 0, off_cnt = 0, off_ent = 0, off_surv = 0, off_msk = 0;
     int64_t off_wtot = 0, off_woff = 0, off_Y = -1, off_W = -1;
     std::vector<int> cap, lds_y, lds_c, scale_off;
@@ -236,7 +236,12 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
             lds += cap;
         }
     }
-    if (!lossy) nscale = s.l_end;
+    if (lossy) {
+        L->lds_scale = lds;                          // 1/sqrt(L) table of the cascade kernel
+        lds += (int)round_up(nscale, 4);
+    } else {
+        nscale = s.l_end;
+    }
     L->n_scale = nscale;
     L->lds_bytes = lds * 4;
     if (L->lds_bytes > 60 * 1024) return SPD_EINVAL;
@@ -324,78 +329,56 @@ int spd_level_widths(const spd_params *params, int32_t level, int32_t *out, int3
     return SPD_OK;
 }
 
-int spd_search(const spd_params *params, const float *x, int64_t ld, int32_t n_dm, int32_t n_in,
-               int32_t n_out, int64_t t0, const float *mean, const float *sigma, float *snr,
-               uint16_t *width, spd_candidate *cand, int64_t cand_cap, int64_t *cand_count,
-               void *workspace, int64_t workspace_bytes, void *hip_stream) {
-    Search s;
-    int st = build_search(params, &s);
-    if (st != SPD_OK) return st;
-    Layout L;
-    st = make_layout(params, s, n_dm, n_in, n_out, &L);
-    if (st != SPD_OK) return st;
-    const spd_plan_info &I = L.info;
-    const bool want_planes = params->flags & SPD_WRITE_PLANES;
-    const bool want_cand = params->flags & SPD_WRITE_CANDIDATES;
-    if (!x || !mean || !sigma || ld < n_in) return SPD_EINVAL;
-    if (want_planes && (!snr || !width)) return SPD_EINVAL;
-    if (want_cand && (cand_cap < 0 || (cand_cap > 0 && !cand) || !cand_count)) return SPD_EINVAL;
-    if (t0 < 0 || (t0 & (((int64_t)1 << I.top_level) - 1))) return SPD_EALIGN;
-    if (!workspace || workspace_bytes < I.workspace_bytes) return SPD_EWORKSPACE;
-    if ((uintptr_t)workspace & 255) return SPD_EALIGN;
-    if (((uintptr_t)snr & 15) || ((uintptr_t)width & 7)) return SPD_EALIGN;
+}  // extern "C"
 
-    char *wsb = static_cast<char *>(workspace);
-    float *scale = reinterpret_cast<float *>(wsb + L.off_scale);
-    uint32_t *evalmask = reinterpret_cast<uint32_t *>(wsb + L.off_mask);
-    uint32_t *slab_cnt = reinterpret_cast<uint32_t *>(wsb + L.off_cnt);
-    uint32_t *slab_ent = reinterpret_cast<uint32_t *>(wsb + L.off_ent);
-    float *Y = want_planes ? snr : reinterpret_cast<float *>(wsb + L.off_Y);
-    uint16_t *W = want_planes ? width : reinterpret_cast<uint16_t *>(wsb + L.off_W);
+namespace {
+
+struct Prepared {
+    Search s;
+    Layout L;
+    char *ws = nullptr;
+    float *Y = nullptr;
+    uint16_t *W = nullptr;
+};
+
+// Shared validation of spd_filter / spd_peaks / spd_search.
+int prepare(const spd_params *params, int32_t n_dm, int32_t n_in, int32_t n_out, float *snr,
+            uint16_t *width, void *workspace, int64_t workspace_bytes, Prepared *P) {
+    int st = build_search(params, &P->s);
+    if (st != SPD_OK) return st;
+    st = make_layout(params, P->s, n_dm, n_in, n_out, &P->L);
+    if (st != SPD_OK) return st;
+    const bool want_planes = params->flags & SPD_WRITE_PLANES;
+    if (want_planes && (!snr || !width)) return SPD_EINVAL;
+    if (!workspace || workspace_bytes < P->L.info.workspace_bytes) return SPD_EWORKSPACE;
+    if ((uintptr_t)workspace & 255) return SPD_EALIGN;
+    if (want_planes && (((uintptr_t)snr & 15) || ((uintptr_t)width & 7))) return SPD_EALIGN;
+    P->ws = static_cast<char *>(workspace);
+    P->Y = want_planes ? snr : reinterpret_cast<float *>(P->ws + P->L.off_Y);
+    P->W = want_planes ? width : reinterpret_cast<uint16_t *>(P->ws + P->L.off_W);
+    return SPD_OK;
+}
+
+int run_filter(const spd_params *params, const Prepared &P, const float *x, int64_t ld,
+               int32_t n_dm, int32_t n_in, int32_t n_out, const float *mean, const float *sigma,
+               void *hip_stream) {
+    const Search &s = P.s;
+    const Layout &L = P.L;
+    const spd_plan_info &I = L.info;
+    const bool want_cand = params->flags & SPD_WRITE_CANDIDATES;
+    uint32_t *slab_cnt = reinterpret_cast<uint32_t *>(P.ws + L.off_cnt);
+    uint32_t *slab_ent = reinterpret_cast<uint32_t *>(P.ws + L.off_ent);
     const int vec_ok = (((uintptr_t)x & 15) == 0) && (ld % 4 == 0);
     const int nlev = I.n_levels;
-    const bool lossy = s.method != SPD_EXHAUSTIVE;
-
-    // 1/sqrt(L) tables
-    {
-        spd::ScaleArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.scale = scale;
-        a.n_levels = nlev;
-        a.l_end = s.l_end;
-        a.exhaustive = !lossy;
-        for (int i = 0; i < nlev && lossy; ++i) {
-            const Level &lv = s.levels[i];
-            a.level_shift[i] = lv.shift;
-            a.level_base[i] = lv.base;
-            a.level_nw[i] = (int)lv.units.size();
-            a.level_off[i] = L.scale_off[i];
-            for (size_t j = 0; j < lv.units.size(); ++j) a.units[i][j] = (uint8_t)lv.units[j];
-        }
-        const int err = spd::launch_scales(a, L.n_scale, hip_stream);
-        if (err) return hip_fail(err);
-    }
-    if (!lossy && !s.dense) {
-        spd::MaskArgs m;
-        std::memset(&m, 0, sizeof(m));
-        m.evalmask = evalmask;
-        m.n_words = (int)ceil_div(s.l_end, 32);
-        for (int w : s.levels[0].widths) m.bits[(w - 1) >> 5] |= 1u << ((w - 1) & 31);
-        const int err = spd::launch_evalmask(m, hip_stream);
-        if (err) return hip_fail(err);
-    }
-
-    // search
-    if (lossy) {
+    if (s.method != SPD_EXHAUSTIVE) {
         spd::LossyArgs a;
         std::memset(&a, 0, sizeof(a));
         a.x = x;
         a.ld = ld;
         a.mean = mean;
         a.sigma = sigma;
-        a.Y = Y;
-        a.W = W;
-        a.scale = scale;
+        a.Y = P.Y;
+        a.W = P.W;
         a.slab_cnt = slab_cnt;
         a.slab_ent = slab_ent;
         a.n_dm = n_dm;
@@ -407,6 +390,8 @@ int spd_search(const spd_params *params, const float *x, int64_t ld, int32_t n_d
         a.max_chunks = L.max_chunks;
         a.vec_ok = vec_ok;
         a.want_cand = want_cand;
+        a.n_scale = L.n_scale;
+        a.lds_scale = L.lds_scale;
         a.threshold = params->threshold;
         for (int i = 0; i < nlev; ++i) {
             const Level &lv = s.levels[i];
@@ -427,67 +412,131 @@ int spd_search(const spd_params *params, const float *x, int64_t ld, int32_t n_d
         }
         const int err = spd::launch_lossy(a, s.method == SPD_BOXDIT, L.lds_bytes, hip_stream);
         if (err) return hip_fail(err);
-    } else {
-        spd::ExhArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.x = x;
-        a.ld = ld;
-        a.mean = mean;
-        a.sigma = sigma;
-        a.Y = Y;
-        a.W = W;
+        return SPD_OK;
+    }
+    float *scale = reinterpret_cast<float *>(P.ws + L.off_scale);
+    uint32_t *evalmask = reinterpret_cast<uint32_t *>(P.ws + L.off_mask);
+    {
+        spd::ScaleArgs a;
         a.scale = scale;
-        a.evalmask = evalmask;
-        a.slab_cnt = slab_cnt;
-        a.slab_ent = slab_ent;
-        a.pitch = I.plane_pitch[0];
-        a.n_dm = n_dm;
-        a.n_in = n_in;
-        a.n_out = n_out;
-        a.l_end = s.l_end;
-        a.n_seg = L.n_seg;
-        a.vec_ok = vec_ok;
-        a.want_cand = want_cand;
-        a.threshold = params->threshold;
-        const int err = spd::launch_exhaustive(a, s.dense, hip_stream);
+        a.n = L.n_scale;
+        const int err = spd::launch_scales(a, hip_stream);
         if (err) return hip_fail(err);
     }
-
-    // candidates
-    if (want_cand) {
-        spd::PeakArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.Y = Y;
-        a.W = W;
-        a.slab_cnt = slab_cnt;
-        a.slab_ent = slab_ent;
-        a.surv = reinterpret_cast<uint32_t *>(wsb + L.off_surv);
-        a.mask = reinterpret_cast<uint64_t *>(wsb + L.off_msk);
-        a.wave_tot = reinterpret_cast<int64_t *>(wsb + L.off_wtot);
-        a.wave_off = reinterpret_cast<int64_t *>(wsb + L.off_woff);
-        a.cand = cand;
-        a.cand_cap = cand_cap;
-        a.cand_count = cand_count;
-        a.t0 = t0;
-        a.n_slabs = L.n_slabs;
-        a.slabs_per_wave = L.slabs_per_wave;
-        a.n_waves = L.n_waves;
-        a.slab_cap = L.slab_cap;
-        a.n_levels = nlev;
-        a.n_dm = n_dm;
-        a.n_seg = L.n_seg;
-        a.seg = L.seg;
-        a.threshold = params->threshold;
-        for (int i = 0; i < nlev; ++i) {
-            a.level_shift[i] = I.level_shift[i];
-            a.level_slots[i] = (int)I.plane_slots[i];
-            a.level_pitch[i] = I.plane_pitch[i];
-            a.level_off[i] = I.plane_offset[i];
-        }
-        const int err = spd::launch_peaks(a, hip_stream);
+    if (!s.dense) {
+        spd::MaskArgs m;
+        std::memset(&m, 0, sizeof(m));
+        m.evalmask = evalmask;
+        m.n_words = (int)ceil_div(s.l_end, 32);
+        for (int w : s.levels[0].widths) m.bits[(w - 1) >> 5] |= 1u << ((w - 1) & 31);
+        const int err = spd::launch_evalmask(m, hip_stream);
         if (err) return hip_fail(err);
     }
+    spd::ExhArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.x = x;
+    a.ld = ld;
+    a.mean = mean;
+    a.sigma = sigma;
+    a.Y = P.Y;
+    a.W = P.W;
+    a.scale = scale;
+    a.evalmask = evalmask;
+    a.slab_cnt = slab_cnt;
+    a.slab_ent = slab_ent;
+    a.pitch = I.plane_pitch[0];
+    a.n_dm = n_dm;
+    a.n_in = n_in;
+    a.n_out = n_out;
+    a.l_end = s.l_end;
+    a.n_seg = L.n_seg;
+    a.vec_ok = vec_ok;
+    a.want_cand = want_cand;
+    a.threshold = params->threshold;
+    const int err = spd::launch_exhaustive(a, s.dense, hip_stream);
+    if (err) return hip_fail(err);
     return SPD_OK;
+}
+
+int run_peaks(const spd_params *params, const Prepared &P, int32_t n_dm, int64_t t0,
+              spd_candidate *cand, int64_t cand_cap, int64_t *cand_count, void *hip_stream) {
+    const Layout &L = P.L;
+    const spd_plan_info &I = L.info;
+    spd::PeakArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.Y = P.Y;
+    a.W = P.W;
+    a.slab_cnt = reinterpret_cast<uint32_t *>(P.ws + L.off_cnt);
+    a.slab_ent = reinterpret_cast<uint32_t *>(P.ws + L.off_ent);
+    a.surv = reinterpret_cast<uint32_t *>(P.ws + L.off_surv);
+    a.mask = reinterpret_cast<uint64_t *>(P.ws + L.off_msk);
+    a.wave_tot = reinterpret_cast<int64_t *>(P.ws + L.off_wtot);
+    a.wave_off = reinterpret_cast<int64_t *>(P.ws + L.off_woff);
+    a.cand = cand;
+    a.cand_cap = cand_cap;
+    a.cand_count = cand_count;
+    a.t0 = t0;
+    a.n_slabs = L.n_slabs;
+    a.slabs_per_wave = L.slabs_per_wave;
+    a.n_waves = L.n_waves;
+    a.slab_cap = L.slab_cap;
+    a.n_levels = I.n_levels;
+    a.n_dm = n_dm;
+    a.n_seg = L.n_seg;
+    a.seg = L.seg;
+    a.threshold = params->threshold;
+    for (int i = 0; i < I.n_levels; ++i) {
+        a.level_shift[i] = I.level_shift[i];
+        a.level_slots[i] = (int)I.plane_slots[i];
+        a.level_pitch[i] = I.plane_pitch[i];
+        a.level_off[i] = I.plane_offset[i];
+    }
+    const int err = spd::launch_peaks(a, hip_stream);
+    if (err) return hip_fail(err);
+    return SPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spd_filter(const spd_params *params, const float *x, int64_t ld, int32_t n_dm, int32_t n_in,
+               int32_t n_out, const float *mean, const float *sigma, float *snr, uint16_t *width,
+               void *workspace, int64_t workspace_bytes, void *hip_stream) {
+    Prepared P;
+    int st = prepare(params, n_dm, n_in, n_out, snr, width, workspace, workspace_bytes, &P);
+    if (st != SPD_OK) return st;
+    if (!x || !mean || !sigma || ld < n_in) return SPD_EINVAL;
+    return run_filter(params, P, x, ld, n_dm, n_in, n_out, mean, sigma, hip_stream);
+}
+
+int spd_peaks(const spd_params *params, int32_t n_dm, int32_t n_in, int32_t n_out, int64_t t0,
+              const float *snr, const uint16_t *width, spd_candidate *cand, int64_t cand_cap,
+              int64_t *cand_count, void *workspace, int64_t workspace_bytes, void *hip_stream) {
+    if (!params || !(params->flags & SPD_WRITE_CANDIDATES)) return SPD_EINVAL;
+    Prepared P;
+    int st = prepare(params, n_dm, n_in, n_out, const_cast<float *>(snr),
+                     const_cast<uint16_t *>(width), workspace, workspace_bytes, &P);
+    if (st != SPD_OK) return st;
+    if (cand_cap < 0 || (cand_cap > 0 && !cand) || !cand_count) return SPD_EINVAL;
+    if (t0 < 0 || (t0 & (((int64_t)1 << P.L.info.top_level) - 1))) return SPD_EALIGN;
+    return run_peaks(params, P, n_dm, t0, cand, cand_cap, cand_count, hip_stream);
+}
+
+int spd_search(const spd_params *params, const float *x, int64_t ld, int32_t n_dm, int32_t n_in,
+               int32_t n_out, int64_t t0, const float *mean, const float *sigma, float *snr,
+               uint16_t *width, spd_candidate *cand, int64_t cand_cap, int64_t *cand_count,
+               void *workspace, int64_t workspace_bytes, void *hip_stream) {
+    Prepared P;
+    int st = prepare(params, n_dm, n_in, n_out, snr, width, workspace, workspace_bytes, &P);
+    if (st != SPD_OK) return st;
+    const bool want_cand = params->flags & SPD_WRITE_CANDIDATES;
+    if (!x || !mean || !sigma || ld < n_in) return SPD_EINVAL;
+    if (want_cand && (cand_cap < 0 || (cand_cap > 0 && !cand) || !cand_count)) return SPD_EINVAL;
+    if (t0 < 0 || (t0 & (((int64_t)1 << P.L.info.top_level) - 1))) return SPD_EALIGN;
+    st = run_filter(params, P, x, ld, n_dm, n_in, n_out, mean, sigma, hip_stream);
+    if (st != SPD_OK || !want_cand) return st;
+    return run_peaks(params, P, n_dm, t0, cand, cand_cap, cand_count, hip_stream);
 }
 
 }  // extern "C"

@@ -48,7 +48,6 @@ struct LossyArgs {
     const float *sigma;
     float *Y;                 // planes (caller's or workspace)
     uint16_t *W;
-    const float *scale;       // 1/sqrt(L) per (level, width)
     uint32_t *slab_cnt;       // [n_levels][n_dm][n_seg]
     uint32_t *slab_ent;       // [...][kSlabCap]
     int32_t n_dm, n_in, n_out, n_levels;
@@ -56,6 +55,8 @@ struct LossyArgs {
     int32_t max_chunks;       // hard bound on streamed chunks per work item
     int32_t vec_ok;           // x rows are 16-byte aligned (float4 loads)
     int32_t want_cand;
+    int32_t n_scale;          // widths over all levels (1/sqrt(L) table in LDS)
+    int32_t lds_scale;        // LDS offset (floats) of that table
     float threshold;
     LevelDesc lv[kMaxLevels];
 };
@@ -80,15 +81,8 @@ struct ExhArgs {
 };
 
 struct ScaleArgs {
-    float *scale;
-    int32_t n_levels;
-    int32_t l_end;            // exhaustive: table length
-    int32_t exhaustive;
-    int32_t level_shift[kMaxLevels];
-    int32_t level_base[kMaxLevels];
-    int32_t level_nw[kMaxLevels];
-    int32_t level_off[kMaxLevels];
-    uint8_t units[kMaxLevels][kMaxLevelWidths];
+    float *scale;             // 1/sqrt(L) for L = 1..n at index L-1 (exhaustive search)
+    int32_t n;
 };
 
 struct MaskArgs {
@@ -124,7 +118,7 @@ struct PeakArgs {
 };
 
 // Launchers (spd_kernels.hip).  Return hipError_t as int.
-int launch_scales(const ScaleArgs &a, int n_total, void *stream);
+int launch_scales(const ScaleArgs &a, void *stream);
 int launch_evalmask(const MaskArgs &a, void *stream);
 int launch_lossy(const LossyArgs &a, bool carry, int lds_bytes, void *stream);
 int launch_exhaustive(const ExhArgs &a, bool dense, void *stream);

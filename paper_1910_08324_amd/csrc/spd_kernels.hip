@@ -23,22 +23,13 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
 }
 
 // ----------------------------------------------------------------------------------------
-// 1/sqrt(L) tables.  Computed in FP64 and rounded once to FP32, so every kernel scales a
-// boxcar sum by the correctly rounded value of 1/sqrt(L) (white-noise scaling, Section 2.1).
+// 1/sqrt(L) table of the exhaustive search.  Computed in FP64 and rounded once to FP32, so
+// every kernel scales a boxcar sum by the correctly rounded 1/sqrt(L) (white-noise scaling,
+// Section 2.1).  The cascade kernel builds its own small table in LDS the same way.
 // ----------------------------------------------------------------------------------------
-__global__ void scales_kernel(const ScaleArgs A, int n_total) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_total) return;
-    double L;
-    if (A.exhaustive) {
-        L = (double)(t + 1);
-    } else {
-        int lev = 0;
-        while (lev + 1 < A.n_levels && t >= A.level_off[lev + 1]) ++lev;
-        int j = t - A.level_off[lev];
-        L = (double)A.level_base[lev] + (double)((int64_t)A.units[lev][j] << A.level_shift[lev]);
-    }
-    A.scale[t] = (float)(1.0 / sqrt(L));
+__global__ void scales_kernel(const ScaleArgs A) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < A.n) A.scale[t] = (float)(1.0 / sqrt((double)(t + 1)));
 }
 
 __global__ void evalmask_kernel(const MaskArgs A) {
@@ -85,6 +76,14 @@ __global__ __launch_bounds__(64) void lossy_kernel(const LossyArgs A) {
         st_cb[lane] = 0;
         st_cw[lane] = 0;
         st_cnt[lane] = 0;
+    }
+    // 1/sqrt(L) of every (level, width), rounded once from FP64 (white-noise scaling)
+    for (int t = lane; t < A.n_scale; t += 64) {
+        int lev = 0;
+        while (lev + 1 < nlev && t >= A.lv[lev + 1].scale_off) ++lev;
+        const LevelDesc &D = A.lv[lev];
+        const double L = (double)D.base + (double)((int64_t)D.units[t - D.scale_off] << lev);   // level index = log2 separation
+        lds[A.lds_scale + t] = (float)(1.0 / sqrt(L));
     }
     __syncthreads();
 
@@ -149,7 +148,7 @@ __global__ __launch_bounds__(64) void lossy_kernel(const LossyArgs A) {
                 const bool pass_carry = CARRY && (k + 1 < nlev);
                 float *cn = pass_carry ? (lds + A.lv[k + 1].lds_c - st_cb[k + 1]) : nullptr;
                 const int ufull = D.ufull;
-                const float *sc = A.scale + D.scale_off;
+                const float *sc = lds + A.lds_scale + D.scale_off;
                 const int64_t rowoff = D.plane_off + (int64_t)d * D.pitch + (s0 >> k);
                 const int64_t slab = ((int64_t)k * A.n_dm + d) * A.n_seg + g;
                 uint32_t cnt = st_cnt[k];
@@ -646,10 +645,9 @@ __global__ __launch_bounds__(256) void peak_scatter_kernel(const PeakArgs A) {
 // ----------------------------------------------------------------------------------------
 // Launchers
 // ----------------------------------------------------------------------------------------
-int launch_scales(const ScaleArgs &a, int n_total, void *stream) {
-    if (n_total <= 0) return 0;
-    hipLaunchKernelGGL(scales_kernel, dim3((n_total + 255) / 256), dim3(256), 0,
-                       (hipStream_t)stream, a, n_total);
+int launch_scales(const ScaleArgs &a, void *stream) {
+    if (a.n <= 0) return 0;
+    hipLaunchKernelGGL(scales_kernel, dim3((a.n + 255) / 256), dim3(256), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 

@@ -80,6 +80,12 @@ def load():
         lib.spd_search.argtypes = [ctypes.POINTER(Params), P, i64, i32, i32, i32, i64, P, P, P, P,
                                    P, i64, P, P, i64, P]
         lib.spd_search.restype = ctypes.c_int
+        lib.spd_filter.argtypes = [ctypes.POINTER(Params), P, i64, i32, i32, i32, P, P, P, P, P,
+                                   i64, P]
+        lib.spd_filter.restype = ctypes.c_int
+        lib.spd_peaks.argtypes = [ctypes.POINTER(Params), i32, i32, i32, i64, P, P, P, i64, P, P,
+                                  i64, P]
+        lib.spd_peaks.restype = ctypes.c_int
         lib.spd_error_string.argtypes = [ctypes.c_int]
         lib.spd_error_string.restype = ctypes.c_char_p
         lib.spd_abi_version.argtypes = []
@@ -271,3 +277,60 @@ def search(x, mean, sigma, cfg: Config, n_in: Optional[int] = None, n_out: Optio
     _check(st, "spd_search")
     out._workspace = workspace
     return out
+
+
+class Runner:
+    """A prepared search: parameters, output buffers and workspace allocated once, so repeated
+    calls only enqueue kernels (for streaming use and for timing).  `filter()` and `peaks()`
+    enqueue the two stages separately; `search()` enqueues both."""
+
+    def __init__(self, x, mean, sigma, cfg: Config, n_in: Optional[int] = None,
+                 n_out: Optional[int] = None, t0: int = 0, cand_cap: int = 1 << 20, stream=None):
+        import torch
+        self.cfg = cfg
+        self.x, self.mean, self.sigma = x, mean, sigma
+        n_dm, n = x.shape
+        self.n_dm, self.n_in = n_dm, (n if n_in is None else int(n_in))
+        self.n_out = self.n_in if n_out is None else int(n_out)
+        self.t0 = int(t0)
+        self.params, self._keep = cfg.params()
+        self.info = plan(cfg, n_dm, self.n_in, self.n_out)
+        dev = x.device
+        snr = width = cand = count = None
+        if cfg.planes:
+            snr = torch.empty(int(self.info.plane_elems), dtype=torch.float32, device=dev)
+            width = torch.empty(int(self.info.plane_elems), dtype=torch.int16, device=dev)
+        if cfg.candidates:
+            cand = torch.empty(max(1, cand_cap) * CANDIDATE_DTYPE.itemsize, dtype=torch.uint8,
+                               device=dev)
+            count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.result = Result(self.info, snr, width, cand, count, n_dm)
+        self.cap = cand_cap if cfg.candidates else 0
+        self.workspace = torch.empty(max(256, int(self.info.workspace_bytes)), dtype=torch.uint8,
+                                     device=dev)
+        self.stream = torch.cuda.current_stream(dev).cuda_stream if stream is None else stream
+        V = ctypes.c_void_p
+        vp = lambda t: V(t.data_ptr()) if t is not None else None
+        self._p = ctypes.byref(self.params)
+        self._x, self._mu, self._sg = vp(x), vp(mean), vp(sigma)
+        self._Y, self._W = vp(snr), vp(width)
+        self._C, self._N = vp(cand), vp(count)
+        self._ws, self._s = vp(self.workspace), V(self.stream)
+        self._ld = x.stride(0)
+        self._lib = load()
+
+    def filter(self):
+        _check(self._lib.spd_filter(self._p, self._x, self._ld, self.n_dm, self.n_in, self.n_out,
+                                    self._mu, self._sg, self._Y, self._W, self._ws,
+                                    self.workspace.numel(), self._s), "spd_filter")
+
+    def peaks(self):
+        _check(self._lib.spd_peaks(self._p, self.n_dm, self.n_in, self.n_out, self.t0, self._Y,
+                                   self._W, self._C, self.cap, self._N, self._ws,
+                                   self.workspace.numel(), self._s), "spd_peaks")
+
+    def search(self):
+        _check(self._lib.spd_search(self._p, self._x, self._ld, self.n_dm, self.n_in, self.n_out,
+                                    self.t0, self._mu, self._sg, self._Y, self._W, self._C,
+                                    self.cap, self._N, self._ws, self.workspace.numel(), self._s),
+               "spd_search")
