@@ -13,7 +13,6 @@
 
 namespace {
 
-using spd::kLossyChunk;
 using spd::kMaxLevels;
 using spd::kMaxLevelWidths;
 
@@ -155,15 +154,103 @@ int build_search(const spd_params *p, Search *s) {
     return SPD_OK;
 }
 
+constexpr int kGroupC = spd::kGroup;
+
+// One launch of the cascade kernel: levels k0 .. k0+J-1 over tiles of T units of its input.
+struct StepPlan {
+    int k0 = 0, J = 0, T = 0, tiles = 0, maxu = 8, lds_bytes = 0, n_rtab = 0;
+    bool has_out = false;
+    int64_t in_len = 0;        // units of the input series per row
+    int64_t out_len = 0;       // units handed to the next step per row
+    int64_t ld_out = 0;        // row pitch of the handed-on series in the workspace
+    int64_t off_out = -1, off_cout = -1;
+    spd::StepLevel lv[spd::kStepMaxLevels + 1];
+};
+
 struct Layout {
     spd_plan_info info;
-    int seg = 0, n_seg = 0, max_chunks = 0, lds_bytes = 0;
+    std::vector<StepPlan> steps;
+    int exh_nseg = 0;
     int64_t n_slabs = 0, slabs_per_wave = 0;
-    int n_waves = 0, slab_cap = 0, n_scale = 0, lds_scale = 0;
+    int n_waves = 0, slab_cap = 0, n_scale = 0;
+    int64_t slab_base[kMaxLevels + 1] = {0};
+    int tiles_per_row[kMaxLevels] = {0};
+    int tile_slots[kMaxLevels] = {0};
     int64_t off_scale = 0, off_mask = 0, off_cnt = 0, off_ent = 0, off_surv = 0, off_msk = 0;
     int64_t off_wtot = 0, off_woff = 0, off_Y = -1, off_W = -1;
-    std::vector<int> cap, lds_y, lds_c, scale_off;
 };
+
+// Lay out one step: units each level must form in a tile, LDS buffers, 1/sqrt(L) tables.
+// Returns the LDS bytes, or -1 if the step cannot be formed with these J and T.
+int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
+    const int K = (int)s.levels.size() - 1;
+    st->k0 = k0;
+    st->J = J;
+    st->T = T;
+    st->has_out = (k0 + J <= K);
+    int umax_all = 1;
+    for (int j = 0; j < J; ++j) umax_all = std::max(umax_all, s.levels[k0 + j].units.back());
+    st->maxu = (int)round_up(umax_all, 4);
+    if ((T >> (J - 1)) % spd::kGroup || (st->has_out && (T >> J) < 1)) return -1;
+    const int top = st->has_out ? J : J - 1;
+    int64_t N[spd::kStepMaxLevels + 1] = {0};
+    for (int j = top; j >= 0; --j) {
+        int64_t need = 0;
+        if (j < J) need = (T >> j) + s.levels[k0 + j].units.back() - 1;
+        else need = T >> J;
+        if (j < top) need = std::max<int64_t>(need, 2 * N[j + 1] + s.levels[k0 + j + 1].cshift);
+        N[j] = round_up(need, 4);
+    }
+    int lds = 0;
+    int64_t capv[spd::kStepMaxLevels + 1] = {0};
+    for (int j = 0; j <= top; ++j) {
+        spd::StepLevel &L = st->lv[j];
+        std::memset(&L, 0, sizeof(L));
+        const Level &lv = s.levels[k0 + j];
+        L.k = lv.shift;
+        L.cshift = j == 0 ? 0 : lv.cshift;
+        L.n_units = (int)N[j];
+        const int64_t cap = (j < J) ? round_up(std::max<int64_t>(N[j], (T >> j) + st->maxu + 8), 4)
+                                    : N[j];
+        L.lds_y = lds;
+        capv[j] = cap;
+        lds += (int)cap;
+        L.base = lv.base;
+        if (j < J) {
+            L.umax = lv.units.back();
+            L.ufull = (k0 + j + 1 <= K) ? s.levels[k0 + j + 1].cshift : 0;
+            for (int u : lv.units) L.evalmask |= 1ull << (u - 1);
+        }
+    }
+    if (s.method == SPD_BOXDIT) {
+        for (int j = 0; j < J; ++j) {
+            if (j == 0 && k0 == 0) continue;
+            st->lv[j].lds_c = lds;
+            lds += T >> j;
+        }
+    }
+    st->n_rtab = 0;
+    const int r0 = lds;
+    for (int j = 0; j < J; ++j) {
+        st->lv[j].lds_r = r0 + st->n_rtab;
+        st->n_rtab += st->lv[j].umax;
+    }
+    lds += (int)round_up(st->n_rtab, 4);
+    st->lds_bytes = lds * 4;
+    // a halo longer than the tile means the tile is too short for these levels
+    if (N[0] - T > T) return -1;
+    // every LDS read of the kernel must land on a unit the tile formed:
+    //   cascade  y_j[n] <- y_{j-1}[2n + cshift], y_{j-1}[2n + cshift + 1],  n < N_j
+    //   banks    y_j[m + u], m < T >> j, u < umax_j;  float4 window reads up to m + umax_j + 7
+    for (int j = 1; j <= top; ++j)
+        if (2 * (N[j] - 1) + st->lv[j].cshift + 1 >= N[j - 1]) return -1;
+    for (int j = 0; j < J; ++j) {
+        const int64_t last_used = (T >> j) - 1 + st->lv[j].umax - 1;
+        const int64_t last_read = (T >> j) - kGroupC + ((st->lv[j].umax - 1) / 4) * 4 + 7;
+        if (last_used >= N[j] || last_read >= capv[j]) return -1;
+    }
+    return st->lds_bytes;
+}
 
 int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in, int32_t n_out,
                 Layout *L) {
@@ -190,80 +277,90 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
     I.plane_elems = off;
 
     const bool lossy = s.method != SPD_EXHAUSTIVE;
-    if (!lossy) {
-        if (p->segment != 0 && p->segment != spd::kExhSlots) return SPD_EINVAL;
-        L->seg = spd::kExhSlots;
-    } else {
-        const int64_t G = std::max<int64_t>(kLossyChunk, (int64_t)4 << K);
-        const int64_t full = round_up(n_out, G);
-        int64_t seg;
-        if (p->segment != 0) {
-            if (p->segment < 0 || p->segment % G) return SPD_EINVAL;
-            seg = std::min<int64_t>(p->segment, full);
-        } else {
-            const int64_t want_items = ceil_div(8192, n_dm);          // fill 256 CUs several times
-            seg = round_up(ceil_div(n_out, want_items), G);
-            const int64_t floor_seg = std::min(full, round_up(4 * (int64_t)s.max_width, G));
-            seg = std::max(seg, floor_seg);
-            seg = std::min(seg, full);
-        }
-        if (seg > (1 << 30)) seg = (int64_t)1 << 30;
-        L->seg = (int)seg;
-    }
-    L->n_seg = (int)ceil_div(n_out, L->seg);
-    I.segment = L->seg;
-    I.n_segments = L->n_seg;
-    if ((int64_t)n_dm * L->n_seg > INT32_MAX) return SPD_EINVAL;
-
-    // LDS windows of the cascade kernel
-    L->cap.assign(nlev, 0);
-    L->lds_y.assign(nlev, 0);
-    L->lds_c.assign(nlev, 0);
-    L->scale_off.assign(nlev, 0);
-    int lds = 0, nscale = 0;
-    for (int i = 0; i < nlev; ++i) {
-        const Level &lv = s.levels[i];
-        L->scale_off[i] = nscale;
-        nscale += (int)lv.widths.size();
-        if (!lossy) continue;
-        const int umax = lv.units.back();
-        const int cap = (int)round_up(ceil_div(kLossyChunk, (int64_t)1 << lv.shift) + umax + 16, 4);
-        L->cap[i] = cap;
-        L->lds_y[i] = lds;
-        lds += cap;
-        if (s.method == SPD_BOXDIT && i > 0) {
-            L->lds_c[i] = lds;
-            lds += cap;
-        }
-    }
-    if (lossy) {
-        L->lds_scale = lds;                          // 1/sqrt(L) table of the cascade kernel
-        lds += (int)round_up(nscale, 4);
-    } else {
-        nscale = s.l_end;
-    }
-    L->n_scale = nscale;
-    L->lds_bytes = lds * 4;
-    if (L->lds_bytes > 60 * 1024) return SPD_EINVAL;
-    L->max_chunks = lossy ? (int)ceil_div((int64_t)L->seg + s.max_width + ((int64_t)4 << K),
-                                          kLossyChunk) + 4
-                          : 0;
-
-    // candidate bookkeeping
-    L->slab_cap = lossy ? spd::kSlabCap : spd::kExhSlabCap;
-    L->n_slabs = (int64_t)(lossy ? nlev : 1) * n_dm * L->n_seg;
-    L->n_waves = (int)std::min<int64_t>(spd::kPeakWaves, L->n_slabs);
-    L->slabs_per_wave = ceil_div(L->n_slabs, L->n_waves);
-    L->n_waves = (int)ceil_div(L->n_slabs, L->slabs_per_wave);
-
     int64_t ws = 0;
     auto take = [&](int64_t bytes) {
         const int64_t at = ws;
         ws += round_up(std::max<int64_t>(bytes, 1), 256);
         return at;
     };
+    if (!lossy) {
+        if (p->segment != 0 && p->segment != spd::kExhSlots) return SPD_EINVAL;
+        L->exh_nseg = (int)ceil_div(n_out, spd::kExhSlots);
+        I.segment = spd::kExhSlots;
+        I.n_segments = L->exh_nseg;
+        L->tiles_per_row[0] = L->exh_nseg;
+        L->tile_slots[0] = spd::kExhSlots;
+        L->n_scale = s.l_end;
+        L->slab_cap = spd::kExhSlabCap;
+    } else {
+        // chain of cascade steps, each covering up to kStepMaxLevels levels
+        const bool fixed_T = p->segment != 0;
+        int T = fixed_T ? p->segment : 4096;
+        if (T < 256 || T > 32768 || T % 256) return SPD_EINVAL;
+        int k0 = 0;
+        int64_t in_len = n_in;
+        while (k0 <= K) {
+            StepPlan st;
+            int J = std::min(spd::kStepMaxLevels, K + 1 - k0);
+            int Tj = T;
+            int lds = -1;
+            for (;;) {
+                lds = plan_step(s, k0, J, Tj, &st);
+                if (lds >= 0 && lds <= 60 * 1024) break;
+                if (J > 1) {
+                    --J;
+                } else if (!fixed_T && Tj > 256) {
+                    Tj >>= 1;
+                    J = std::min(spd::kStepMaxLevels, K + 1 - k0);
+                } else {
+                    return SPD_EINVAL;
+                }
+            }
+            st.in_len = in_len;
+            const int64_t slots0 = I.plane_slots[k0];
+            int64_t tiles = ceil_div(slots0, st.T);
+            if (st.has_out) {
+                const int k1 = k0 + st.J;
+                const int64_t usable = std::max<int64_t>(0, ((int64_t)n_in - s.levels[k1].base) >> k1);
+                tiles = std::max(tiles, ceil_div(usable, st.T >> st.J));
+                st.out_len = tiles * (st.T >> st.J);
+                st.ld_out = round_up(st.out_len, 64);
+            }
+            if (tiles * n_dm > INT32_MAX) return SPD_EINVAL;
+            st.tiles = (int)tiles;
+            for (int j = 0; j < st.J; ++j) {
+                L->tiles_per_row[k0 + j] = st.tiles;
+                L->tile_slots[k0 + j] = st.T >> j;
+                st.lv[j].slots = (int)I.plane_slots[k0 + j];
+                st.lv[j].plane_off = I.plane_offset[k0 + j];
+                st.lv[j].pitch = I.plane_pitch[k0 + j];
+            }
+            in_len = st.out_len;
+            L->steps.push_back(st);
+            k0 += st.J;
+        }
+        I.segment = L->steps[0].T;
+        I.n_segments = L->steps[0].tiles;
+        L->slab_cap = spd::kSlabCap;
+        for (StepPlan &st : L->steps) {
+            if (st.has_out) {
+                st.off_out = take((int64_t)n_dm * st.ld_out * 4);
+                if (s.method == SPD_BOXDIT) st.off_cout = take((int64_t)n_dm * st.ld_out * 4);
+            }
+        }
+    }
+    L->slab_base[0] = 0;
+    for (int k = 0; k < nlev; ++k)
+        L->slab_base[k + 1] = L->slab_base[k] + (int64_t)n_dm * L->tiles_per_row[k];
+    L->n_slabs = L->slab_base[nlev];
+    for (StepPlan &st : L->steps)
+        for (int j = 0; j < st.J; ++j) st.lv[j].slab_base = L->slab_base[st.k0 + j];
+    L->n_waves = (int)std::min<int64_t>(spd::kPeakWaves, L->n_slabs);
+    L->slabs_per_wave = ceil_div(L->n_slabs, L->n_waves);
+    L->n_waves = (int)ceil_div(L->n_slabs, L->slabs_per_wave);
+
     // the exhaustive kernel's masked tail group reads up to kExhGroup entries past the tables
-    L->off_scale = take(((int64_t)nscale + spd::kExhGroup) * 4);
+    L->off_scale = take(((int64_t)L->n_scale + spd::kExhGroup) * 4);
     L->off_mask = take(s.dense ? 4 : (ceil_div(s.l_end, 32) + 4) * 4);
     L->off_cnt = take(L->n_slabs * 4);
     L->off_ent = take(L->n_slabs * L->slab_cap * 4);
@@ -369,49 +466,48 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
     uint32_t *slab_cnt = reinterpret_cast<uint32_t *>(P.ws + L.off_cnt);
     uint32_t *slab_ent = reinterpret_cast<uint32_t *>(P.ws + L.off_ent);
     const int vec_ok = (((uintptr_t)x & 15) == 0) && (ld % 4 == 0);
-    const int nlev = I.n_levels;
     if (s.method != SPD_EXHAUSTIVE) {
-        spd::LossyArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.x = x;
-        a.ld = ld;
-        a.mean = mean;
-        a.sigma = sigma;
-        a.Y = P.Y;
-        a.W = P.W;
-        a.slab_cnt = slab_cnt;
-        a.slab_ent = slab_ent;
-        a.n_dm = n_dm;
-        a.n_in = n_in;
-        a.n_out = n_out;
-        a.n_levels = nlev;
-        a.seg = L.seg;
-        a.n_seg = L.n_seg;
-        a.max_chunks = L.max_chunks;
-        a.vec_ok = vec_ok;
-        a.want_cand = want_cand;
-        a.n_scale = L.n_scale;
-        a.lds_scale = L.lds_scale;
-        a.threshold = params->threshold;
-        for (int i = 0; i < nlev; ++i) {
-            const Level &lv = s.levels[i];
-            spd::LevelDesc &D = a.lv[i];
-            D.cshift = lv.cshift;
-            D.nw = (int)lv.units.size();
-            D.umax = lv.units.back();
-            D.ufull = (i + 1 < nlev) ? s.levels[i + 1].cshift : 0;
-            D.base = lv.base;
-            D.cap = L.cap[i];
-            D.lds_y = L.lds_y[i];
-            D.lds_c = L.lds_c[i];
-            D.scale_off = L.scale_off[i];
-            D.slots = (int)I.plane_slots[i];
-            D.plane_off = I.plane_offset[i];
-            D.pitch = I.plane_pitch[i];
-            for (size_t j = 0; j < lv.units.size(); ++j) D.units[j] = (uint8_t)lv.units[j];
+        const float *in = x;
+        int64_t ld_in = ld;
+        const float *cin = nullptr;
+        for (size_t si = 0; si < L.steps.size(); ++si) {
+            const StepPlan &st = L.steps[si];
+            spd::StepArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.in = in;
+            a.cin = cin;
+            a.out = st.has_out ? reinterpret_cast<float *>(P.ws + st.off_out) : nullptr;
+            a.cout = (st.has_out && st.off_cout >= 0) ? reinterpret_cast<float *>(P.ws + st.off_cout)
+                                                       : nullptr;
+            a.mean = mean;
+            a.sigma = sigma;
+            a.Y = P.Y;
+            a.W = P.W;
+            a.slab_cnt = slab_cnt;
+            a.slab_ent = slab_ent;
+            a.ld_in = ld_in;
+            a.ld_cin = ld_in;
+            a.ld_out = st.ld_out;
+            a.n_dm = n_dm;
+            a.n_in = n_in;
+            a.in_len = (int32_t)st.in_len;
+            a.T = st.T;
+            a.n_tiles = st.tiles;
+            a.J = st.J;
+            a.has_out = st.has_out;
+            a.normalise = si == 0;
+            a.carry = s.method == SPD_BOXDIT;
+            a.vec_ok = si == 0 ? vec_ok : 1;
+            a.want_cand = want_cand;
+            a.n_rtab = st.n_rtab;
+            a.threshold = params->threshold;
+            for (int j = 0; j <= st.J && j <= spd::kStepMaxLevels; ++j) a.lv[j] = st.lv[j];
+            const int err = spd::launch_step(a, st.lds_bytes, hip_stream);
+            if (err) return hip_fail(err);
+            in = a.out;
+            ld_in = st.ld_out;
+            cin = a.cout;
         }
-        const int err = spd::launch_lossy(a, s.method == SPD_BOXDIT, L.lds_bytes, hip_stream);
-        if (err) return hip_fail(err);
         return SPD_OK;
     }
     float *scale = reinterpret_cast<float *>(P.ws + L.off_scale);
@@ -449,7 +545,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
     a.n_in = n_in;
     a.n_out = n_out;
     a.l_end = s.l_end;
-    a.n_seg = L.n_seg;
+    a.n_seg = L.exh_nseg;
     a.vec_ok = vec_ok;
     a.want_cand = want_cand;
     a.threshold = params->threshold;
@@ -482,15 +578,16 @@ int run_peaks(const spd_params *params, const Prepared &P, int32_t n_dm, int64_t
     a.slab_cap = L.slab_cap;
     a.n_levels = I.n_levels;
     a.n_dm = n_dm;
-    a.n_seg = L.n_seg;
-    a.seg = L.seg;
     a.threshold = params->threshold;
     for (int i = 0; i < I.n_levels; ++i) {
         a.level_shift[i] = I.level_shift[i];
         a.level_slots[i] = (int)I.plane_slots[i];
         a.level_pitch[i] = I.plane_pitch[i];
         a.level_off[i] = I.plane_offset[i];
+        a.tiles_per_row[i] = L.tiles_per_row[i];
+        a.tile_slots[i] = L.tile_slots[i];
     }
+    for (int i = 0; i <= I.n_levels; ++i) a.slab_base[i] = L.slab_base[i];
     const int err = spd::launch_peaks(a, hip_stream);
     if (err) return hip_fail(err);
     return SPD_OK;

@@ -10,55 +10,66 @@ namespace spd {
 
 constexpr int kMaxLevels = SPD_MAX_LEVELS;
 constexpr int kMaxLevelWidths = SPD_MAX_LEVEL_WIDTHS;
-constexpr int kLossyChunk = 1024;    // input samples streamed per step of the cascade kernel
-constexpr int kExhSlots = 256;       // output slots per exhaustive work item (64 lanes x 4)
-constexpr int kExhBlock = 512;       // widths per LDS window refill in the exhaustive kernel
-constexpr int kExhGroup = 64;        // widths per max-only group (argmax recovered afterwards)
-constexpr int kSlabCap = 64;         // pre-candidates kept per (level, row, segment), lossy
-constexpr int kExhSlabCap = 16;      // pre-candidates kept per exhaustive work item
-constexpr int kPeakWaves = 4096;     // waves of the peak-finder pass (slab ranges per wave)
+constexpr int kStepMaxLevels = 6;     // levels handled by one launch of the cascade kernel
+constexpr int kStepThreads = 256;     // threads per tile work-group
+constexpr int kGroup = 4;             // consecutive slots evaluated together by one thread
+constexpr int kExhSlots = 256;        // output slots per exhaustive work item (64 lanes x 4)
+constexpr int kExhBlock = 512;        // widths per LDS window refill in the exhaustive kernel
+constexpr int kExhGroup = 64;         // widths per max-only group (argmax recovered afterwards)
+constexpr int kSlabCap = 32;          // pre-candidates kept per (level, row, tile)
+constexpr int kExhSlabCap = 16;       // pre-candidates kept per exhaustive work item
+constexpr int kPeakWaves = 8192;      // waves of the peak-finder passes
 
-// One separation level of a BoxDIT / IGRID search (boxcars every 2^k samples).
-// Level k works on the decimated series y_k: unit n of y_k is the sum of the 2^k raw samples
-// starting at n 2^k + base (relative to the work item's first sample).  It is made from level
-// k-1 as y_k[n] = y_{k-1}[2n + cshift] + y_{k-1}[2n + cshift + 1].
-// Widths of the level: base + units[j] 2^k, j < nw (ascending).  For BoxDIT every boxcar of the
-// level also includes the carried sum of its first `base` samples (the previous iteration's
-// longest boxcar).
-struct LevelDesc {
-    int32_t cshift;          // cascade shift in units of level k-1 (BoxDIT: L^{k-1}_max)
-    int32_t nw;              // widths evaluated at this level
-    int32_t umax;            // units[nw-1]
-    int32_t ufull;           // units summed for the carry handed to level k+1 (BoxDIT)
-    int32_t base;            // raw offset of unit 0 (BoxDIT: sum_{j<k} 2^j L^j_max)
-    int32_t cap;             // LDS capacity (floats) of this level's window
-    int32_t lds_y;           // LDS offset (floats) of the y_k window
-    int32_t lds_c;           // LDS offset (floats) of the carry window (BoxDIT)
-    int32_t scale_off;       // offset of this level's 1/sqrt(L) table in the scale buffer
-    int32_t slots;           // ceil(n_out / 2^k)
-    int64_t plane_off;       // element offset of this level's plane
-    int64_t pitch;           // elements between rows
-    uint8_t units[kMaxLevelWidths];
+// One level of a cascade step.  The step's input series is y_{k0} (for the first step the
+// normalised samples); level j of the step is the absolute level k = k0 + j, whose unit n is
+// the sum of 2^k samples starting at n 2^k + base (BoxDIT: base = off_k, the width of the
+// carried prefix; IGRID: 0).  Level j is made from level j-1 as
+//     y_j[n] = y_{j-1}[2n + cshift] + y_{j-1}[2n + cshift + 1].
+// The boxcars of the level at slot m are  carry[m] + sum_{u < U} y_j[m + u]  for every unit
+// count U with bit (U-1) of `evalmask` set (BoxDIT adds the carried prefix; IGRID has none).
+struct StepLevel {
+    int32_t k;               // absolute level index = log2 of the boxcar separation
+    int32_t cshift;          // cascade shift in units of level j-1
+    int32_t n_units;         // units of this level formed in a tile (LDS buffer length)
+    int32_t lds_y;           // LDS offset (floats) of the unit buffer
+    int32_t lds_c;           // LDS offset (floats) of the carry buffer (BoxDIT)
+    int32_t umax;            // widest unit count evaluated (0: output-only level)
+    int32_t ufull;           // units in the carry handed to level j+1 (BoxDIT)
+    int32_t base;            // raw width offset of the level
+    int32_t slots;           // plane slots per row = ceil(n_out / 2^k)
+    int32_t lds_r;           // LDS offset of 1/sqrt(base + U 2^k), U = 1..umax
+    uint64_t evalmask;       // bit U-1: U units is one of the level's widths
+    int64_t plane_off;       // element offset of the level's plane
+    int64_t pitch;           // elements between rows of the plane
+    int64_t slab_base;       // first pre-candidate slab of the level
 };
 
-struct LossyArgs {
-    const float *x;
-    int64_t ld;
+struct StepArgs {
+    const float *in;          // step input series [n_dm][ld_in] (raw samples for the first step)
+    const float *cin;         // carried prefixes of the first level [n_dm][ld_cin] (BoxDIT, k0 > 0)
+    float *out;               // series for the next step [n_dm][ld_out], or null
+    float *cout;              // carried prefixes for the next step, or null
     const float *mean;
     const float *sigma;
     float *Y;                 // planes (caller's or workspace)
     uint16_t *W;
-    uint32_t *slab_cnt;       // [n_levels][n_dm][n_seg]
-    uint32_t *slab_ent;       // [...][kSlabCap]
-    int32_t n_dm, n_in, n_out, n_levels;
-    int32_t seg, n_seg;       // samples per work item, work items per row
-    int32_t max_chunks;       // hard bound on streamed chunks per work item
-    int32_t vec_ok;           // x rows are 16-byte aligned (float4 loads)
+    uint32_t *slab_cnt;
+    uint32_t *slab_ent;
+    int64_t ld_in, ld_cin, ld_out;
+    int32_t n_dm;
+    int32_t n_in;             // raw samples per row (valid-only boundary)
+    int32_t in_len;           // units of the input series available per row
+    int32_t T;                // tile length in units of the input series
+    int32_t n_tiles;          // tiles per row
+    int32_t J;                // bank levels in this step
+    int32_t has_out;          // produce level J for the next step
+    int32_t normalise;        // first step: z = (x - mean) / sigma on load
+    int32_t carry;            // BoxDIT
+    int32_t vec_ok;           // rows of `in` are 16-byte aligned
     int32_t want_cand;
-    int32_t n_scale;          // widths over all levels (1/sqrt(L) table in LDS)
-    int32_t lds_scale;        // LDS offset (floats) of that table
+    int32_t n_rtab;           // entries of the 1/sqrt(L) tables
     float threshold;
-    LevelDesc lv[kMaxLevels];
+    StepLevel lv[kStepMaxLevels + 1];
 };
 
 struct ExhArgs {
@@ -91,11 +102,14 @@ struct MaskArgs {
     uint32_t bits[SPD_MAX_LIST_LEND / 32];
 };
 
+// Pre-candidate slabs: one per (level, row, tile); the slabs of level k start at slab_base[k]
+// and are ordered by row, then tile.  Tile t of level k covers slots
+// [t tile_slots[k], min((t+1) tile_slots[k], slots[k])).
 struct PeakArgs {
     const float *Y;
     const uint16_t *W;
-    const uint32_t *slab_cnt;
-    const uint32_t *slab_ent;
+    uint32_t *slab_cnt;
+    uint32_t *slab_ent;       // sorted in place by the count pass
     uint32_t *surv;           // survivors per slab
     uint64_t *mask;           // survivor bitmask per slab (entries mode)
     int64_t *wave_tot;
@@ -108,11 +122,13 @@ struct PeakArgs {
     int64_t slabs_per_wave;
     int32_t n_waves;
     int32_t slab_cap;
-    int32_t n_levels, n_dm, n_seg;
-    int32_t seg;              // level-0 samples per segment
+    int32_t n_levels, n_dm;
     float threshold;
     int32_t level_shift[kMaxLevels];
     int32_t level_slots[kMaxLevels];
+    int32_t tiles_per_row[kMaxLevels];
+    int32_t tile_slots[kMaxLevels];
+    int64_t slab_base[kMaxLevels + 1];
     int64_t level_pitch[kMaxLevels];
     int64_t level_off[kMaxLevels];
 };
@@ -120,7 +136,7 @@ struct PeakArgs {
 // Launchers (spd_kernels.hip).  Return hipError_t as int.
 int launch_scales(const ScaleArgs &a, void *stream);
 int launch_evalmask(const MaskArgs &a, void *stream);
-int launch_lossy(const LossyArgs &a, bool carry, int lds_bytes, void *stream);
+int launch_step(const StepArgs &a, int lds_bytes, void *stream);
 int launch_exhaustive(const ExhArgs &a, bool dense, void *stream);
 int launch_peaks(const PeakArgs &a, void *stream);
 const char *hip_error_text(int err);

@@ -1,9 +1,9 @@
 // Boxcar single-pulse search kernels for gfx950 (CDNA4, wave64).
 //
-// lossy_kernel       BoxDIT and IGRID: one wave streams one (DM row, time segment) work item
-//                    through an on-chip decimation cascade.  Every input sample is read from HBM
-//                    once (plus the look-ahead halo of the segment), every plane value is written
-//                    once, and no intermediate level ever leaves LDS.
+// step_kernel        BoxDIT and IGRID: one launch per step of up to six separation levels.
+//                    A work-group takes one tile of a DM row into LDS, forms the decimated
+//                    levels on chip and evaluates every level's width set; only the planes and
+//                    the last level (1/64 of the input) go back to HBM.
 // exh_kernel         exhaustive search (every width 1..L_end): one wave per 256 output slots,
 //                    4 consecutive starts per lane, the input window streamed through an LDS ring.
 // peak_* kernels     thresholded 3x3 peak finding over the per-level planes, with output in
@@ -38,219 +38,237 @@ __global__ void evalmask_kernel(const MaskArgs A) {
 }
 
 // ----------------------------------------------------------------------------------------
-// BoxDIT / IGRID cascade kernel.
+// BoxDIT / IGRID cascade: one launch per step of up to kStepMaxLevels levels.
 //
-// Work item = (row d, segment g): output slots [g seg / 2^k, min((g+1) seg / 2^k, slots_k)) of
-// every level k.  The wave streams the row forward from s0 = g seg in chunks of kLossyChunk
-// samples.  For each level it keeps, in LDS, a window of its decimated series y_k (and for
-// BoxDIT the carried prefix sums), and it emits a slot as soon as every unit that slot's
-// widest boxcar needs has been formed.  State per level (all wave-uniform):
-//   a[k]   units of y_k formed so far          e[k]  next slot to emit
-//   yb[k]  unit held at window index 0          cb[k] slot held at carry-window index 0
-//   cw[k]  carries written so far (BoxDIT)      cnt[k] pre-candidates found (slab fill)
-// After each chunk every window is compacted to its live tail so the LDS footprint stays at
-// about 2 * chunk + levels * (widest unit count) floats.
+// Work-group = (DM row d, tile t) of 256 threads.  The tile covers T units of the step's
+// input series (the normalised samples in the first step, the decimated series y_{k0}
+// afterwards) plus the halo its widest boxcars reach.  The whole tile lives in LDS:
+//   1. load the window (coalesced float4), normalising z = (x - mu) / sigma in the first step;
+//   2. form the decimated levels in place, one pass and one barrier per level;
+//   3. evaluate every level's width set at every slot of the tile, 4 consecutive slots per
+//      thread from a register window, writing the SNR/width planes (BoxDIT adds the carried
+//      prefix and hands each level's longest boxcar on as the next level's prefix);
+//   4. hand the last formed level (and its prefixes) to the next step through HBM.
+// Slots whose SNR is above the threshold and not below its time neighbours are recorded as
+// pre-candidates for the peak finder (a superset of the final candidates).
 // ----------------------------------------------------------------------------------------
-template <bool CARRY>
-__global__ __launch_bounds__(64) void lossy_kernel(const LossyArgs A) {
+__global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
     extern __shared__ float lds[];
-    __shared__ int st_a[kMaxLevels], st_e[kMaxLevels], st_yb[kMaxLevels], st_cb[kMaxLevels];
-    __shared__ int st_cw[kMaxLevels];
-    __shared__ uint32_t st_cnt[kMaxLevels];
+    __shared__ uint32_t st_cnt[kStepMaxLevels];
 
-    const int lane = threadIdx.x;
-    const int d = blockIdx.x / A.n_seg;
-    const int g = blockIdx.x - d * A.n_seg;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int d = blockIdx.x / A.n_tiles;
+    const int tile = blockIdx.x - d * A.n_tiles;
     if (d >= A.n_dm) return;
-    const int nlev = A.n_levels;
-    const int s0 = g * A.seg;                       // first sample of the segment (row coords)
-    const float *xr = A.x + (int64_t)d * A.ld;
-    const float mu = A.mean[d];
-    const float inv = 1.0f / A.sigma[d];
-    const float thr = A.threshold;
+    const int T = A.T;
+    const int64_t u0 = (int64_t)tile * T;
 
-    if (lane < nlev) {
-        st_a[lane] = 0;
-        st_e[lane] = 0;
-        st_yb[lane] = 0;
-        st_cb[lane] = 0;
-        st_cw[lane] = 0;
-        st_cnt[lane] = 0;
+    // 1/sqrt(L) of every width of the step, rounded once from FP64 (white-noise scaling)
+    {
+        const int r0 = A.lv[0].lds_r;
+        for (int t = tid; t < A.n_rtab; t += kStepThreads) {
+            int j = 0;
+            while (j + 1 < A.J && r0 + t >= A.lv[j + 1].lds_r) ++j;
+            const StepLevel &L = A.lv[j];
+            const int U = r0 + t - L.lds_r + 1;
+            const double w = (double)L.base + (double)((int64_t)U << L.k);
+            lds[r0 + t] = (float)(1.0 / sqrt(w));
+        }
     }
-    // 1/sqrt(L) of every (level, width), rounded once from FP64 (white-noise scaling)
-    for (int t = lane; t < A.n_scale; t += 64) {
-        int lev = 0;
-        while (lev + 1 < nlev && t >= A.lv[lev + 1].scale_off) ++lev;
-        const LevelDesc &D = A.lv[lev];
-        const double L = (double)D.base + (double)((int64_t)D.units[t - D.scale_off] << lev);   // level index = log2 separation
-        lds[A.lds_scale + t] = (float)(1.0 / sqrt(L));
-    }
-    __syncthreads();
+    if (tid < kStepMaxLevels) st_cnt[tid] = 0;
 
-    constexpr int C = kLossyChunk;
-    for (int ch = 0; ch < A.max_chunks; ++ch) {
-        // ---- 1. load + normalise chunk ch into the level-0 window: z = (x - mu) / sigma
-        {
-            const int a0 = st_a[0];
-            float *y0 = lds + A.lv[0].lds_y - st_yb[0] + a0;
-            const int r0 = s0 + ch * C;
-#pragma unroll
-            for (int q = 0; q < C / 256; ++q) {
-                const int j = q * 256 + lane * 4;
-                const int r = r0 + j;
-                float4 v;
-                if (A.vec_ok && r + 3 < A.n_in) {
-                    v = *reinterpret_cast<const float4 *>(xr + r);
+    // ---- 1. window of the input series (and the first level's carried prefixes)
+    {
+        const float *inr = A.in + (int64_t)d * A.ld_in;
+        float mu = 0.0f, inv = 1.0f;
+        if (A.normalise) {
+            mu = A.mean[d];
+            inv = 1.0f / A.sigma[d];
+        }
+        const int N0 = A.lv[0].n_units;
+        float *y0 = lds + A.lv[0].lds_y;
+        const int64_t len = A.in_len;
+        for (int i = tid * 4; i < N0; i += kStepThreads * 4) {
+            const int64_t r = u0 + i;
+            float4 v;
+            if (A.vec_ok && r + 3 < len) {
+                v = *reinterpret_cast<const float4 *>(inr + r);
+                if (A.normalise) {
                     v.x = (v.x - mu) * inv;
                     v.y = (v.y - mu) * inv;
                     v.z = (v.z - mu) * inv;
                     v.w = (v.w - mu) * inv;
-                } else {
-                    v.x = (r + 0 < A.n_in) ? (xr[r + 0] - mu) * inv : 0.0f;
-                    v.y = (r + 1 < A.n_in) ? (xr[r + 1] - mu) * inv : 0.0f;
-                    v.z = (r + 2 < A.n_in) ? (xr[r + 2] - mu) * inv : 0.0f;
-                    v.w = (r + 3 < A.n_in) ? (xr[r + 3] - mu) * inv : 0.0f;
                 }
-                *reinterpret_cast<float4 *>(y0 + j) = v;
+            } else {
+                float e[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    e[q] = 0.0f;
+                    if (r + q < len) e[q] = A.normalise ? (inr[r + q] - mu) * inv : inr[r + q];
+                }
+                v = make_float4(e[0], e[1], e[2], e[3]);
             }
-            __syncthreads();
-            if (lane == 0) st_a[0] = a0 + C;
-            __syncthreads();
+            *reinterpret_cast<float4 *>(y0 + i) = v;
         }
-
-        // ---- 2. decimation cascade: y_k[n] = y_{k-1}[2n + cshift] + y_{k-1}[2n + cshift + 1]
-        for (int k = 1; k < nlev; ++k) {
-            const int cs = A.lv[k].cshift;
-            const int ap = st_a[k - 1];
-            const int aold = st_a[k];
-            const int anew = ap >= cs + 2 ? (ap - cs) >> 1 : 0;
-            const float *yp = lds + A.lv[k - 1].lds_y - st_yb[k - 1];
-            float *yk = lds + A.lv[k].lds_y - st_yb[k];
-            for (int n = aold + lane; n < anew; n += 64) {
-                const int src = 2 * n + cs;
-                yk[n] = yp[src] + yp[src + 1];
+        if (A.carry && A.cin) {
+            const float *cr = A.cin + (int64_t)d * A.ld_cin;
+            float *c0 = lds + A.lv[0].lds_c;
+            for (int i = tid; i < T; i += kStepThreads) {
+                const int64_t m = u0 + i;
+                c0[i] = (m < A.lv[0].slots) ? cr[m] : 0.0f;
             }
-            __syncthreads();
-            if (lane == 0) st_a[k] = anew > aold ? anew : aold;
-            __syncthreads();
         }
+    }
+    __syncthreads();
 
-        // ---- 3. emit every slot whose widest boxcar is complete, level by level
-        bool all_done = true;
-        for (int k = 0; k < nlev; ++k) {
-            const LevelDesc &D = A.lv[k];
-            const int endk = min(A.seg >> k, D.slots - (s0 >> k));
-            const int e = st_e[k];
-            const int hi = min(st_a[k] - D.umax + 1, endk);
-            if (hi > e) {
-                const float *yk = lds + D.lds_y - st_yb[k];
-                const float *ck = lds + D.lds_c - st_cb[k];
-                const bool pass_carry = CARRY && (k + 1 < nlev);
-                float *cn = pass_carry ? (lds + A.lv[k + 1].lds_c - st_cb[k + 1]) : nullptr;
-                const int ufull = D.ufull;
-                const float *sc = lds + A.lds_scale + D.scale_off;
-                const int64_t rowoff = D.plane_off + (int64_t)d * D.pitch + (s0 >> k);
-                const int64_t slab = ((int64_t)k * A.n_dm + d) * A.n_seg + g;
-                uint32_t cnt = st_cnt[k];
-                for (int mb = e; mb < hi; mb += 64) {
-                    const int m = mb + lane;
-                    const bool act = m < hi;
-                    float best = SPD_NEG_INF;
-                    int bw = 0;
-                    if (act) {
-                        float X = (CARRY && k > 0) ? ck[m] : 0.0f;   // level 0 has no carried prefix
-                        const int64_t s = (int64_t)s0 + ((int64_t)m << k);
-                        const int64_t room = (int64_t)A.n_in - s;   // widths <= room are valid
-                        int u = 0;
-                        for (int j = 0; j < D.nw; ++j) {
-                            const int uj = D.units[j];
-                            for (; u < uj; ++u) X += yk[m + u];
-                            const int Lw = D.base + (uj << k);
-                            if (Lw <= room) {
-                                const float v = X * sc[j];
-                                if (v > best) {
-                                    best = v;
-                                    bw = Lw;
+    // ---- 2. decimation cascade
+    const int jtop = A.has_out ? A.J : A.J - 1;
+    for (int j = 1; j <= jtop; ++j) {
+        const float *yp = lds + A.lv[j - 1].lds_y + A.lv[j].cshift;
+        float *yq = lds + A.lv[j].lds_y;
+        const int nq = A.lv[j].n_units;
+        for (int n = tid; n < nq; n += kStepThreads) {
+            const float2 p = *reinterpret_cast<const float2 *>(yp + 2 * n);
+            yq[n] = p.x + p.y;
+        }
+        __syncthreads();
+    }
+
+    // ---- 3. width sets of every level
+    for (int j = 0; j < A.J; ++j) {
+        const StepLevel &L = A.lv[j];
+        const int Sj = T >> j;
+        const int64_t ms0 = (int64_t)tile * Sj;          // absolute slot of tile slot 0
+        const int ngroups = Sj / kGroup;
+        const float *yj = lds + L.lds_y;
+        const float *cj = lds + L.lds_c;
+        const bool has_carry = A.carry && (j > 0 || A.cin != nullptr);
+        const bool pass_carry = A.carry && (j + 1 < A.J || A.has_out);
+        float *cn_lds = (A.carry && j + 1 < A.J) ? lds + A.lv[j + 1].lds_c : nullptr;
+        float *cn_glb = (A.carry && j + 1 == A.J && A.has_out)
+                            ? A.cout + (int64_t)d * A.ld_out + ((int64_t)tile * (T >> A.J)) : nullptr;
+        const int k = L.k;
+        const int umax = L.umax;
+        const uint64_t emask = L.evalmask;
+        const int64_t slab = L.slab_base + (int64_t)d * A.n_tiles + tile;
+        for (int gb = 0; gb < ngroups; gb += kStepThreads) {
+            const int g = gb + tid;
+            const int m0 = g * kGroup;
+            const int64_t ma = ms0 + m0;
+            const bool act = (g < ngroups) && (ma < L.slots);
+            float best[kGroup];
+            int bw[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                best[q] = SPD_NEG_INF;
+                bw[q] = 0;
+            }
+            if (act) {
+                float X[kGroup];
+                int64_t room[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    X[q] = has_carry ? cj[m0 + q] : 0.0f;
+                    room[q] = (int64_t)A.n_in - ((ma + q) << k);
+                }
+                const bool fast = ((ma + kGroup - 1) << k) + L.base + ((int64_t)umax << k) <= A.n_in;
+                // sliding window y_j[m0 + u4 .. m0 + u4 + 8) over blocks of 4 unit counts
+                float4 wa = *reinterpret_cast<const float4 *>(yj + m0);
+                for (int u4 = 0; u4 < umax; u4 += 4) {
+                    const float4 wb = *reinterpret_cast<const float4 *>(yj + m0 + u4 + 4);
+                    const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int u = u4 + t;
+                        if (u >= umax) break;
+#pragma unroll
+                        for (int q = 0; q < kGroup; ++q) X[q] += w[q + t];
+                        if ((emask >> u) & 1ull) {
+                            const float r = lds[L.lds_r + u];
+                            const int Lw = L.base + ((u + 1) << k);
+#pragma unroll
+                            for (int q = 0; q < kGroup; ++q) {
+                                float v = X[q] * r;
+                                if (!fast && Lw > room[q]) v = SPD_NEG_INF;
+                                if (v > best[q]) {
+                                    best[q] = v;
+                                    bw[q] = Lw;
                                 }
                             }
                         }
-                        if (pass_carry && !(m & 1)) {
-                            for (; u < ufull; ++u) X += yk[m + u];
-                            cn[m >> 1] = X;
-                        }
-                        A.Y[rowoff + m] = best;
-                        A.W[rowoff + m] = (uint16_t)bw;
-                    }
-                    if (A.want_cand) {
-                        const bool hit = act && best > thr;
-                        const uint64_t b = __ballot(hit);
-                        if (b) {
-                            if (hit) {
-                                const uint32_t pos = cnt + __popcll(b & lanes_below(lane));
-                                if (pos < kSlabCap)
-                                    A.slab_ent[slab * kSlabCap + pos] = (uint32_t)((s0 >> k) + m);
+                        if (pass_carry && u + 1 == L.ufull) {
+                            // this level's longest boxcar is the next level's carried prefix
+                            if (cn_lds) {
+                                cn_lds[(m0 >> 1) + 0] = X[0];
+                                cn_lds[(m0 >> 1) + 1] = X[2];
+                            } else if (cn_glb) {
+                                cn_glb[(m0 >> 1) + 0] = X[0];
+                                cn_glb[(m0 >> 1) + 1] = X[2];
                             }
-                            cnt += __popcll(b);
+                        }
+                    }
+                    wa = wb;
+                }
+                float *Yr = A.Y + L.plane_off + (int64_t)d * L.pitch + ma;
+                uint16_t *Wr = A.W + L.plane_off + (int64_t)d * L.pitch + ma;
+                if (ma + kGroup <= L.slots) {
+                    *reinterpret_cast<float4 *>(Yr) = make_float4(best[0], best[1], best[2], best[3]);
+                    *reinterpret_cast<uint2 *>(Wr) =
+                        make_uint2((uint32_t)bw[0] | ((uint32_t)bw[1] << 16),
+                                   (uint32_t)bw[2] | ((uint32_t)bw[3] << 16));
+                } else {
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q)
+                        if (ma + q < L.slots) {
+                            Yr[q] = best[q];
+                            Wr[q] = (uint16_t)bw[q];
+                        }
+                }
+            }
+            if (A.want_cand) {
+                // time neighbours: inside the group, or the adjacent groups of the neighbouring
+                // lanes; unknown neighbours (wave edges) are treated as -inf (conservative)
+                float left = __shfl_up(best[kGroup - 1], 1);
+                float right = __shfl_down(best[0], 1);
+                if (lane == 0) left = SPD_NEG_INF;
+                if (lane == 63) right = SPD_NEG_INF;
+                int nh = 0;
+                bool hit[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    const float l = q > 0 ? best[q - 1] : left;
+                    const float rr = q + 1 < kGroup ? best[q + 1] : right;
+                    hit[q] = act && (ma + q < L.slots) && best[q] > A.threshold && best[q] > l &&
+                             best[q] >= rr;
+                    nh += hit[q];
+                }
+                if (nh) {
+                    uint32_t pos = atomicAdd(&st_cnt[j], (uint32_t)nh);
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) {
+                        if (hit[q]) {
+                            if (pos < (uint32_t)kSlabCap)
+                                A.slab_ent[slab * kSlabCap + pos] = (uint32_t)(ma + q);
+                            ++pos;
                         }
                     }
                 }
-                __syncthreads();
-                if (lane == 0) {
-                    st_e[k] = hi;
-                    st_cnt[k] = cnt;
-                    if (pass_carry) st_cw[k + 1] = (hi + 1) >> 1;
-                }
-                __syncthreads();
             }
-            if (max(e, hi) < endk) all_done = false;
         }
-        if (all_done) break;
-
-        // ---- 4. compact every window to its live tail
-        for (int k = 0; k < nlev; ++k) {
-            const LevelDesc &D = A.lv[k];
-            const int endk = min(A.seg >> k, D.slots - (s0 >> k));
-            const int a = st_a[k];
-            const int e = st_e[k];
-            int lo = a;
-            if (e < endk) lo = min(lo, e);
-            if (k + 1 < nlev) lo = min(lo, 2 * st_a[k + 1] + A.lv[k + 1].cshift);
-            if (k == 0) lo &= ~3;                        // keep float4 alignment of loads
-            const int yb = st_yb[k];
-            float *yw = lds + D.lds_y;
-            const int len = a - lo;
-            float v0 = 0.0f, v1 = 0.0f;
-            if (lane < len) v0 = yw[lo - yb + lane];
-            if (lane + 64 < len) v1 = yw[lo - yb + lane + 64];
-            int clen = 0, clo = 0;
-            float c0 = 0.0f, c1 = 0.0f;
-            if (CARRY && k > 0) {
-                clo = e;
-                clen = max(0, st_cw[k] - clo);
-                float *cwin = lds + D.lds_c;
-                const int cb = st_cb[k];
-                if (lane < clen) c0 = cwin[clo - cb + lane];
-                if (lane + 64 < clen) c1 = cwin[clo - cb + lane + 64];
-            }
-            __syncthreads();
-            if (lane < len) yw[lane] = v0;
-            if (lane + 64 < len) yw[lane + 64] = v1;
-            if (CARRY && k > 0) {
-                float *cwin = lds + D.lds_c;
-                if (lane < clen) cwin[lane] = c0;
-                if (lane + 64 < clen) cwin[lane + 64] = c1;
-            }
-            __syncthreads();
-            if (lane == 0) {
-                st_yb[k] = lo;
-                if (CARRY && k > 0) st_cb[k] = clo;
-            }
-            __syncthreads();
-        }
+        if (A.carry) __syncthreads();
     }
 
-    if (A.want_cand && lane < nlev)
-        A.slab_cnt[((int64_t)lane * A.n_dm + d) * A.n_seg + g] = st_cnt[lane];
+    // ---- 4. hand on the last formed level
+    if (A.has_out) {
+        const float *yJ = lds + A.lv[A.J].lds_y;
+        float *o = A.out + (int64_t)d * A.ld_out + (int64_t)tile * (T >> A.J);
+        for (int n = tid; n < (T >> A.J); n += kStepThreads) o[n] = yJ[n];
+    }
+    if (A.want_cand) {
+        __syncthreads();
+        if (tid < A.J) A.slab_cnt[A.lv[tid].slab_base + (int64_t)d * A.n_tiles + tile] = st_cnt[tid];
+    }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -422,27 +440,33 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
         }
     }
     if (A.want_cand) {
+        // pre-candidates: above the threshold and not below either time neighbour (neighbours
+        // held by other work items are unknown and treated as -inf)
+        float left = __shfl_up(best[3], 1);
+        float right = __shfl_down(best[0], 1);
+        if (lane == 0) left = SPD_NEG_INF;
+        if (lane == 63) right = SPD_NEG_INF;
         bool hit[4];
         int mine = 0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            hit[v] = (m0 + v < A.n_out) && best[v] > A.threshold;
+            const float l = v > 0 ? best[v - 1] : left;
+            const float r = v < 3 ? best[v + 1] : right;
+            hit[v] = (m0 + v < A.n_out) && best[v] > A.threshold && best[v] > l && best[v] >= r;
             mine += hit[v];
         }
         const uint64_t any = __ballot(mine > 0);
-        uint32_t base = 0;
+        uint32_t total = 0;
         if (any) {
-            // exclusive prefix of `mine` over lanes (lane-major, then v)
-            int pre = mine;
+            int pre = mine;                              // inclusive prefix over lanes
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 const int t = __shfl_up(pre, off);
                 if (lane >= off) pre += t;
             }
-            const int total = __shfl(pre, 63);
-            pre -= mine;
+            total = (uint32_t)__shfl(pre, 63);
+            int pos = pre - mine;
             const int64_t slab = (int64_t)d * A.n_seg + g;
-            int pos = pre;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 if (hit[v]) {
@@ -450,19 +474,19 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
                     ++pos;
                 }
             }
-            base = (uint32_t)total;
         }
-        if (lane == 0) A.slab_cnt[(int64_t)d * A.n_seg + g] = base;
+        if (lane == 0) A.slab_cnt[(int64_t)d * A.n_seg + g] = total;
     }
 }
 
 // ----------------------------------------------------------------------------------------
 // Peak finding (candidate selection).  A slot is a candidate iff its SNR is above the
 // threshold and it passes the 3x3 neighbour test (strict against neighbours earlier in
-// row-major order, non-strict against later ones).  Pre-candidates (SNR above threshold) were
-// collected per (level, row, segment) slab by the search kernel in slot order; a slab that
-// overflowed is rescanned densely over its slot range.  Three passes keep the output in
-// (level, dm, start) order without sorting: per-wave survivor counts, one scan, scatter.
+// row-major order, non-strict against later ones).  The search kernels recorded, per
+// (level, row, tile) slab, the slots above the threshold that are not below their time
+// neighbours; a slab that overflowed is rescanned densely over its tile.  Three passes keep the
+// output in (level, dm, start) order without a global sort: per-wave survivor counts (each
+// slab's entries sorted in the wave), one scan, scatter.
 // ----------------------------------------------------------------------------------------
 __device__ __forceinline__ bool peak_test(const PeakArgs &A, int k, int d, int m, float y) {
     const float *P = A.Y + A.level_off[k];
@@ -486,20 +510,39 @@ __device__ __forceinline__ bool peak_test(const PeakArgs &A, int k, int d, int m
 }
 
 struct SlabPos {
-    int k, d, g;
+    int k, d, t, mlo, mhi;
 };
 
 __device__ __forceinline__ SlabPos slab_decode(const PeakArgs &A, int64_t s) {
     SlabPos p;
-    p.g = (int)(s % A.n_seg);
-    const int64_t r = s / A.n_seg;
-    p.d = (int)(r % A.n_dm);
-    p.k = (int)(r / A.n_dm);
+    int k = 0;
+    while (k + 1 < A.n_levels && s >= A.slab_base[k + 1]) ++k;
+    const int64_t r = s - A.slab_base[k];
+    p.k = k;
+    p.d = (int)(r / A.tiles_per_row[k]);
+    p.t = (int)(r - (int64_t)p.d * A.tiles_per_row[k]);
+    p.mlo = p.t * A.tile_slots[k];
+    p.mhi = min(p.mlo + A.tile_slots[k], A.level_slots[k]);
     return p;
 }
 
 __device__ __forceinline__ float plane_at(const PeakArgs &A, int k, int d, int m) {
     return A.Y[A.level_off[k] + (int64_t)d * A.level_pitch[k] + m];
+}
+
+__device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key, int lane) {
+    // bitonic sort of one key per lane, ascending across the 64 lanes
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t other = (uint32_t)__shfl_xor((int)key, j);
+            const bool asc = (lane & k) == 0;
+            const bool low = (lane & j) == 0;
+            key = (asc == low) ? min(key, other) : max(key, other);
+        }
+    }
+    return key;
 }
 
 __global__ __launch_bounds__(256) void peak_count_kernel(const PeakArgs A) {
@@ -518,26 +561,26 @@ __global__ __launch_bounds__(256) void peak_count_kernel(const PeakArgs A) {
             const int l = __ffsll((unsigned long long)nz) - 1;
             nz &= nz - 1;
             const int64_t ss = sb + l;
-            const uint32_t cc = __shfl(c, l);
+            const uint32_t cc = (uint32_t)__shfl((int)c, l);
             const SlabPos p = slab_decode(A, ss);
             uint32_t nsurv = 0;
             uint64_t msk = 0;
             if (cc <= (uint32_t)A.slab_cap) {
+                uint32_t key = (lane < (int)cc) ? A.slab_ent[ss * A.slab_cap + lane] : 0xffffffffu;
+                key = wave_sort_u32(key, lane);
                 bool ok = false;
                 if (lane < (int)cc) {
-                    const int m = (int)A.slab_ent[ss * A.slab_cap + lane];
+                    A.slab_ent[ss * A.slab_cap + lane] = key;
+                    const int m = (int)key;
                     ok = peak_test(A, p.k, p.d, m, plane_at(A, p.k, p.d, m));
                 }
                 msk = __ballot(ok);
                 nsurv = __popcll(msk);
             } else {
-                const int segk = A.seg >> A.level_shift[p.k];
-                const int mlo = p.g * segk;
-                const int mhi = min(mlo + segk, A.level_slots[p.k]);
-                for (int mb = mlo; mb < mhi; mb += 64) {
+                for (int mb = p.mlo; mb < p.mhi; mb += 64) {
                     const int m = mb + lane;
                     bool ok = false;
-                    if (m < mhi) {
+                    if (m < p.mhi) {
                         const float y = plane_at(A, p.k, p.d, m);
                         ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
                     }
@@ -609,7 +652,7 @@ __global__ __launch_bounds__(256) void peak_scatter_kernel(const PeakArgs A) {
             const int l = __ffsll((unsigned long long)nz) - 1;
             nz &= nz - 1;
             const int64_t ss = sb + l;
-            const uint32_t nsurv = __shfl(sv, l);
+            const uint32_t nsurv = (uint32_t)__shfl((int)sv, l);
             const uint32_t cc = A.slab_cnt[ss];
             const SlabPos p = slab_decode(A, ss);
             if (cc <= (uint32_t)A.slab_cap) {
@@ -620,15 +663,12 @@ __global__ __launch_bounds__(256) void peak_scatter_kernel(const PeakArgs A) {
                              plane_at(A, p.k, p.d, m));
                 }
             } else {
-                const int segk = A.seg >> A.level_shift[p.k];
-                const int mlo = p.g * segk;
-                const int mhi = min(mlo + segk, A.level_slots[p.k]);
                 int64_t run = 0;
-                for (int mb = mlo; mb < mhi; mb += 64) {
+                for (int mb = p.mlo; mb < p.mhi; mb += 64) {
                     const int m = mb + lane;
                     bool ok = false;
                     float y = 0.0f;
-                    if (m < mhi) {
+                    if (m < p.mhi) {
                         y = plane_at(A, p.k, p.d, m);
                         ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
                     }
@@ -657,12 +697,9 @@ int launch_evalmask(const MaskArgs &a, void *stream) {
     return (int)hipGetLastError();
 }
 
-int launch_lossy(const LossyArgs &a, bool carry, int lds_bytes, void *stream) {
-    const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_seg));
-    if (carry)
-        hipLaunchKernelGGL(lossy_kernel<true>, grid, dim3(64), lds_bytes, (hipStream_t)stream, a);
-    else
-        hipLaunchKernelGGL(lossy_kernel<false>, grid, dim3(64), lds_bytes, (hipStream_t)stream, a);
+int launch_step(const StepArgs &a, int lds_bytes, void *stream) {
+    const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_tiles));
+    hipLaunchKernelGGL(step_kernel, grid, dim3(kStepThreads), lds_bytes, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 

@@ -134,3 +134,21 @@ def test_search_argument_errors_before_any_launch(lib):
     assert _search_raw(lib, cfg, ws=(1 << 30) + 8) == spd.SPD_EALIGN
     assert _search_raw(lib, spd.Config("bd5", 64)) == spd.SPD_EINVAL
     assert b"t0" in lib.spd_error_string(spd.SPD_EALIGN)
+
+
+@pytest.mark.parametrize("method", ["ig1", "ig2", "ig3", "bd8", "bd16", "bd32", "dit", "exh"])
+def test_plan_accepts_wide_range(lib, method):
+    """The planner finds a launch geometry (and passes its own LDS-bounds self-check) for every
+    L_end, row length and tile size in range."""
+    segs = [0] if method == "exh" else [0, 256, 512, 1024, 2048, 4096, 8192, 16384]
+    for l_end in (1, 2, 5, 64, 255, 256, 1000, 4096, 8192, 8193, 30000, 65535):
+        for n in (1, 7, 1000, 4097, 65536, 262144, 1 << 22):
+            for seg in segs:
+                cfg = spd.Config(method, l_end, segment=seg)
+                try:
+                    info = spd.plan(cfg, 3, n, n)
+                except spd.SpdError as e:
+                    # a fixed tile too short for the widest levels is the only allowed refusal
+                    assert seg != 0 and e.status == spd.SPD_EINVAL, (l_end, n, seg)
+                    continue
+                assert info.workspace_bytes > 0
