@@ -125,7 +125,7 @@ def main():
         torch.cuda.synchronize()
         copy_bytes = x.numel() * 4
         y = torch.empty_like(x)
-        y.copy_(x)
+        torch.mul(x, 1.0, out=y)            # plain streaming kernel: reads and writes copy_bytes
         torch.cuda.synchronize()
         print(json.dumps({"probe": "ok", "method": args.method, "search_launches": 4,
                           "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes,

@@ -30,6 +30,7 @@ struct Search {
     bool dense = true;        // exhaustive over every width 1..l_end
     std::vector<Level> levels;
     int max_width = 0;
+    int fam = 0;              // compiled-in width patterns of the kernel (see family_mask)
 };
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -137,8 +138,18 @@ int build_search(const spd_params *p, Search *s) {
         s->levels.push_back(lv);
     } else if (p->method == SPD_BOXDIT) {
         st = build_boxdit(p, s);
+        if (st == SPD_OK) {
+            bool same = true;
+            for (int i = 1; i < p->n_boxdit_lmax; ++i) same = same && p->boxdit_lmax[i] == p->boxdit_lmax[0];
+            const int L0 = p->boxdit_lmax[0];
+            if (same) s->fam = L0 == 8 ? 4 : L0 == 16 ? 5 : L0 == 32 ? 6 : 0;
+        }
     } else if (p->method == SPD_IGRID) {
         st = build_igrid(p, s);
+        const int P = p->igrid_layers ? p->igrid_layers : (1 << (p->igrid_depth + 1));
+        const int d = p->igrid_depth;
+        if (d >= 1 && d <= 3 && P == (1 << (d + 1))) s->fam = d;
+        if (d == 0 && P == 1) s->fam = 7;
     } else {
         return SPD_EINVAL;
     }
@@ -158,13 +169,14 @@ constexpr int kGroupC = spd::kGroup;
 
 // One launch of the cascade kernel: levels k0 .. k0+J-1 over tiles of T units of its input.
 struct StepPlan {
-    int k0 = 0, J = 0, T = 0, tiles = 0, maxu = 8, lds_bytes = 0, n_rtab = 0;
+    int k0 = 0, J = 0, T = 0, tiles = 0, maxu = 8, lds_bytes = 0;
     bool has_out = false;
     int64_t in_len = 0;        // units of the input series per row
     int64_t out_len = 0;       // units handed to the next step per row
     int64_t ld_out = 0;        // row pitch of the handed-on series in the workspace
     int64_t off_out = -1, off_cout = -1;
     spd::StepLevel lv[spd::kStepMaxLevels + 1];
+    float rtab[spd::kStepMaxLevels][spd::kMaxLevelWidths] = {{0}};
 };
 
 struct Layout {
@@ -220,6 +232,11 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
             L.umax = lv.units.back();
             L.ufull = (k0 + j + 1 <= K) ? s.levels[k0 + j + 1].cshift : 0;
             for (int u : lv.units) L.evalmask |= 1ull << (u - 1);
+            if (s.fam && L.evalmask == spd::family_mask(s.fam, 1)) L.pattern = 1;
+            else if (s.fam && L.evalmask == spd::family_mask(s.fam, 2)) L.pattern = 2;
+            // 1/sqrt(L) for every unit count of the level, rounded once from FP64
+            for (int u = 1; u <= L.umax; ++u)
+                st->rtab[j][u - 1] = (float)(1.0 / std::sqrt((double)lv.base + std::ldexp((double)u, lv.shift)));
         }
     }
     if (s.method == SPD_BOXDIT) {
@@ -229,13 +246,6 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
             lds += T >> j;
         }
     }
-    st->n_rtab = 0;
-    const int r0 = lds;
-    for (int j = 0; j < J; ++j) {
-        st->lv[j].lds_r = r0 + st->n_rtab;
-        st->n_rtab += st->lv[j].umax;
-    }
-    lds += (int)round_up(st->n_rtab, 4);
     st->lds_bytes = lds * 4;
     // a halo longer than the tile means the tile is too short for these levels
     if (N[0] - T > T) return -1;
@@ -246,7 +256,9 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
         if (2 * (N[j] - 1) + st->lv[j].cshift + 1 >= N[j - 1]) return -1;
     for (int j = 0; j < J; ++j) {
         const int64_t last_used = (T >> j) - 1 + st->lv[j].umax - 1;
-        const int64_t last_read = (T >> j) - kGroupC + ((st->lv[j].umax - 1) / 4) * 4 + 7;
+        const int64_t um = st->lv[j].umax;
+        const int64_t last_read = (T >> j) - kGroupC +
+                                  std::max(((um - 1) / 4) * 4 + 7, round_up(um + 3, 4) - 1);
         if (last_used >= N[j] || last_read >= capv[j]) return -1;
     }
     return st->lds_bytes;
@@ -499,10 +511,10 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
             a.carry = s.method == SPD_BOXDIT;
             a.vec_ok = si == 0 ? vec_ok : 1;
             a.want_cand = want_cand;
-            a.n_rtab = st.n_rtab;
             a.threshold = params->threshold;
             for (int j = 0; j <= st.J && j <= spd::kStepMaxLevels; ++j) a.lv[j] = st.lv[j];
-            const int err = spd::launch_step(a, st.lds_bytes, hip_stream);
+            std::memcpy(a.rtab, st.rtab, sizeof(a.rtab));
+            const int err = spd::launch_step(a, s.fam, st.lds_bytes, hip_stream);
             if (err) return hip_fail(err);
             in = a.out;
             ld_in = st.ld_out;

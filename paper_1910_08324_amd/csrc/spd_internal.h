@@ -37,7 +37,7 @@ struct StepLevel {
     int32_t ufull;           // units in the carry handed to level j+1 (BoxDIT)
     int32_t base;            // raw width offset of the level
     int32_t slots;           // plane slots per row = ceil(n_out / 2^k)
-    int32_t lds_r;           // LDS offset of 1/sqrt(base + U 2^k), U = 1..umax
+    int32_t pattern;         // 1, 2: the family's compiled-in width pattern; 0: generic
     uint64_t evalmask;       // bit U-1: U units is one of the level's widths
     int64_t plane_off;       // element offset of the level's plane
     int64_t pitch;           // elements between rows of the plane
@@ -67,9 +67,9 @@ struct StepArgs {
     int32_t carry;            // BoxDIT
     int32_t vec_ok;           // rows of `in` are 16-byte aligned
     int32_t want_cand;
-    int32_t n_rtab;           // entries of the 1/sqrt(L) tables
     float threshold;
     StepLevel lv[kStepMaxLevels + 1];
+    float rtab[kStepMaxLevels][kMaxLevelWidths];   // 1/sqrt(base + U 2^k) at [j][U-1]
 };
 
 struct ExhArgs {
@@ -136,7 +136,10 @@ struct PeakArgs {
 // Launchers (spd_kernels.hip).  Return hipError_t as int.
 int launch_scales(const ScaleArgs &a, void *stream);
 int launch_evalmask(const MaskArgs &a, void *stream);
-int launch_step(const StepArgs &a, int lds_bytes, void *stream);
+int launch_step(const StepArgs &a, int fam, int lds_bytes, void *stream);
+// unit-count mask of a family's compiled-in pattern (1 or 2); families: 1-3 IG(1..3),
+// 4-6 BD-8/16/32, 7 DIT, 0 none
+uint64_t family_mask(int fam, int pattern);
 int launch_exhaustive(const ExhArgs &a, bool dense, void *stream);
 int launch_peaks(const PeakArgs &a, void *stream);
 const char *hip_error_text(int err);

@@ -51,7 +51,119 @@ __global__ void evalmask_kernel(const MaskArgs A) {
 //   4. hand the last formed level (and its prefixes) to the next step through HBM.
 // Slots whose SNR is above the threshold and not below its time neighbours are recorded as
 // pre-candidates for the peak finder (a superset of the final candidates).
+//
+// The width sets of the paper's configurations are compiled in (FAM selects one): the unit
+// counts of a level are then constants, so the bank is straight-line code with 4 VALU
+// operations per (slot, width) plus one add per (slot, unit).  Other width sets, and groups
+// near the end of the data where some widths do not fit, take the generic path.
 // ----------------------------------------------------------------------------------------
+
+// unit-count bitmask (bit U-1) of IGRID IG(d) with P layers: level 0 and level >= 1
+__host__ __device__ constexpr uint64_t ig_mask_l0(int P, int d) {
+    uint64_t m = 0;
+    for (int W = 1; W <= P; W <<= 1) {
+        const int inc = (W >> d) > 1 ? (W >> d) : 1;
+        for (int q = 0; q < (1 << d); ++q)
+            if (W + q * inc < 2 * W) m |= 1ull << (W + q * inc - 1);
+    }
+    return m;
+}
+__host__ __device__ constexpr uint64_t ig_mask_lk(int P, int d) {
+    uint64_t m = 0;
+    for (int q = 0; q < (1 << d); ++q) m |= 1ull << (P + q * (P >> d) - 1);
+    return m;
+}
+__host__ __device__ constexpr uint64_t run_mask(int L) { return L >= 64 ? ~0ull : ((1ull << L) - 1); }
+
+// Compiled-in width patterns of each family: (UMAX, MASK) for pattern 1 and pattern 2.
+template <int FAM> struct Fam;
+template <> struct Fam<0> { static constexpr int U1 = 1, U2 = 1; static constexpr uint64_t M1 = 1, M2 = 1; };
+template <> struct Fam<1> { static constexpr int U1 = 6, U2 = 6;
+                            static constexpr uint64_t M1 = ig_mask_l0(4, 1), M2 = ig_mask_lk(4, 1); };
+template <> struct Fam<2> { static constexpr int U1 = 14, U2 = 14;
+                            static constexpr uint64_t M1 = ig_mask_l0(8, 2), M2 = ig_mask_lk(8, 2); };
+template <> struct Fam<3> { static constexpr int U1 = 30, U2 = 30;
+                            static constexpr uint64_t M1 = ig_mask_l0(16, 3), M2 = ig_mask_lk(16, 3); };
+template <> struct Fam<4> { static constexpr int U1 = 8, U2 = 8;
+                            static constexpr uint64_t M1 = run_mask(8), M2 = run_mask(8); };
+template <> struct Fam<5> { static constexpr int U1 = 16, U2 = 16;
+                            static constexpr uint64_t M1 = run_mask(16), M2 = run_mask(16); };
+template <> struct Fam<6> { static constexpr int U1 = 32, U2 = 32;
+                            static constexpr uint64_t M1 = run_mask(32), M2 = run_mask(32); };
+template <> struct Fam<7> { static constexpr int U1 = 1, U2 = 1; static constexpr uint64_t M1 = 1, M2 = 1; };
+
+// All widths of the group fit: straight-line evaluation of a compiled-in width pattern.
+// X enters holding the carried prefixes and leaves holding the sum over UMAX units.
+// bu receives the unit count of the best width (0 if none).
+template <int UMAX, uint64_t MASK>
+__device__ __forceinline__ void bank_fixed(const float *y, const float *rt, float X[kGroup],
+                                           float best[kGroup], int bu[kGroup]) {
+    constexpr int NW = (kGroup + UMAX - 1 + 3) / 4;
+    float w[4 * NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        const float4 v = *reinterpret_cast<const float4 *>(y + 4 * q);
+        w[4 * q + 0] = v.x;
+        w[4 * q + 1] = v.y;
+        w[4 * q + 2] = v.z;
+        w[4 * q + 3] = v.w;
+    }
+#pragma unroll
+    for (int u = 0; u < UMAX; ++u) {
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) X[q] += w[q + u];
+        if (((MASK >> u) & 1ull) != 0) {        // folded after unrolling
+            const float r = rt[u];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const float v = X[q] * r;
+                const bool gt = v > best[q];
+                best[q] = gt ? v : best[q];
+                bu[q] = gt ? (u + 1) : bu[q];
+            }
+        }
+    }
+}
+
+// Any width set, with the valid-only check per slot.  Xc receives the sum over `ufull` units
+// (the carry handed to the next BoxDIT level).
+__device__ __forceinline__ void bank_generic(const float *y, const float *rt, int umax,
+                                             uint64_t emask, int ufull, int k, int base,
+                                             const int64_t room[kGroup], float X[kGroup],
+                                             float Xc[kGroup], float best[kGroup],
+                                             int bu[kGroup]) {
+    float4 wa = *reinterpret_cast<const float4 *>(y);
+    for (int u4 = 0; u4 < umax; u4 += 4) {
+        const float4 wb = *reinterpret_cast<const float4 *>(y + u4 + 4);
+        const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int u = u4 + t;
+            if (u >= umax) break;
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) X[q] += w[q + t];
+            if ((emask >> u) & 1ull) {
+                const float r = rt[u];
+                const int64_t Lw = (int64_t)base + ((int64_t)(u + 1) << k);
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    float v = X[q] * r;
+                    if (Lw > room[q]) v = SPD_NEG_INF;
+                    const bool gt = v > best[q];
+                    best[q] = gt ? v : best[q];
+                    bu[q] = gt ? (u + 1) : bu[q];
+                }
+            }
+            if (u + 1 == ufull) {
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) Xc[q] = X[q];
+            }
+        }
+        wa = wb;
+    }
+}
+
+template <bool FIRST, int FAM>
 __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
     extern __shared__ float lds[];
     __shared__ uint32_t st_cnt[kStepMaxLevels];
@@ -63,26 +175,13 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
     if (d >= A.n_dm) return;
     const int T = A.T;
     const int64_t u0 = (int64_t)tile * T;
-
-    // 1/sqrt(L) of every width of the step, rounded once from FP64 (white-noise scaling)
-    {
-        const int r0 = A.lv[0].lds_r;
-        for (int t = tid; t < A.n_rtab; t += kStepThreads) {
-            int j = 0;
-            while (j + 1 < A.J && r0 + t >= A.lv[j + 1].lds_r) ++j;
-            const StepLevel &L = A.lv[j];
-            const int U = r0 + t - L.lds_r + 1;
-            const double w = (double)L.base + (double)((int64_t)U << L.k);
-            lds[r0 + t] = (float)(1.0 / sqrt(w));
-        }
-    }
     if (tid < kStepMaxLevels) st_cnt[tid] = 0;
 
     // ---- 1. window of the input series (and the first level's carried prefixes)
     {
         const float *inr = A.in + (int64_t)d * A.ld_in;
         float mu = 0.0f, inv = 1.0f;
-        if (A.normalise) {
+        if (FIRST) {
             mu = A.mean[d];
             inv = 1.0f / A.sigma[d];
         }
@@ -94,7 +193,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
             float4 v;
             if (A.vec_ok && r + 3 < len) {
                 v = *reinterpret_cast<const float4 *>(inr + r);
-                if (A.normalise) {
+                if (FIRST) {
                     v.x = (v.x - mu) * inv;
                     v.y = (v.y - mu) * inv;
                     v.z = (v.z - mu) * inv;
@@ -105,13 +204,13 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     e[q] = 0.0f;
-                    if (r + q < len) e[q] = A.normalise ? (inr[r + q] - mu) * inv : inr[r + q];
+                    if (r + q < len) e[q] = FIRST ? (inr[r + q] - mu) * inv : inr[r + q];
                 }
                 v = make_float4(e[0], e[1], e[2], e[3]);
             }
             *reinterpret_cast<float4 *>(y0 + i) = v;
         }
-        if (A.carry && A.cin) {
+        if (!FIRST && A.carry && A.cin) {
             const float *cr = A.cin + (int64_t)d * A.ld_cin;
             float *c0 = lds + A.lv[0].lds_c;
             for (int i = tid; i < T; i += kStepThreads) {
@@ -139,118 +238,107 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
     for (int j = 0; j < A.J; ++j) {
         const StepLevel &L = A.lv[j];
         const int Sj = T >> j;
-        const int64_t ms0 = (int64_t)tile * Sj;          // absolute slot of tile slot 0
+        const int ms0 = tile * Sj;                         // absolute slot of tile slot 0
         const int ngroups = Sj / kGroup;
         const float *yj = lds + L.lds_y;
         const float *cj = lds + L.lds_c;
         const bool has_carry = A.carry && (j > 0 || A.cin != nullptr);
-        const bool pass_carry = A.carry && (j + 1 < A.J || A.has_out);
-        float *cn_lds = (A.carry && j + 1 < A.J) ? lds + A.lv[j + 1].lds_c : nullptr;
-        float *cn_glb = (A.carry && j + 1 == A.J && A.has_out)
-                            ? A.cout + (int64_t)d * A.ld_out + ((int64_t)tile * (T >> A.J)) : nullptr;
+        const bool to_lds = A.carry && (j + 1 < A.J);
+        const bool to_glb = A.carry && (j + 1 == A.J) && A.has_out;
+        float *cn = to_lds ? lds + A.lv[j + 1].lds_c
+                           : (to_glb ? A.cout + (int64_t)d * A.ld_out + (int64_t)tile * (T >> A.J)
+                                     : nullptr);
         const int k = L.k;
         const int umax = L.umax;
-        const uint64_t emask = L.evalmask;
-        const int64_t slab = L.slab_base + (int64_t)d * A.n_tiles + tile;
+        const int base = L.base;
+        const int pat = L.pattern;
+        const float *rt = A.rtab[j];
+        float *rowY = A.Y + L.plane_off + (int64_t)d * L.pitch;
+        uint16_t *rowW = A.W + L.plane_off + (int64_t)d * L.pitch;
+        // a group is "fast" when the widest boxcar of its last slot ends inside the data
+        const int64_t fast_lim = (int64_t)A.n_in - base - ((int64_t)umax << k);
         for (int gb = 0; gb < ngroups; gb += kStepThreads) {
             const int g = gb + tid;
             const int m0 = g * kGroup;
-            const int64_t ma = ms0 + m0;
+            const int ma = ms0 + m0;
             const bool act = (g < ngroups) && (ma < L.slots);
             float best[kGroup];
-            int bw[kGroup];
+            int bu[kGroup];
 #pragma unroll
             for (int q = 0; q < kGroup; ++q) {
                 best[q] = SPD_NEG_INF;
-                bw[q] = 0;
+                bu[q] = 0;
             }
             if (act) {
-                float X[kGroup];
-                int64_t room[kGroup];
+                float X[kGroup], Xc[kGroup];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    X[q] = has_carry ? cj[m0 + q] : 0.0f;
-                    room[q] = (int64_t)A.n_in - ((ma + q) << k);
+                for (int q = 0; q < kGroup; ++q) X[q] = has_carry ? cj[m0 + q] : 0.0f;
+                const bool fast = ((int64_t)(ma + kGroup - 1) << k) <= fast_lim;
+                if (FAM != 0 && fast && pat == 1) {
+                    bank_fixed<Fam<FAM>::U1, Fam<FAM>::M1>(yj + m0, rt, X, best, bu);
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) Xc[q] = X[q];
+                } else if (FAM != 0 && fast && pat == 2) {
+                    bank_fixed<Fam<FAM>::U2, Fam<FAM>::M2>(yj + m0, rt, X, best, bu);
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) Xc[q] = X[q];
+                } else {
+                    int64_t room[kGroup];
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) room[q] = (int64_t)A.n_in - ((int64_t)(ma + q) << k);
+                    bank_generic(yj + m0, rt, umax, L.evalmask, L.ufull, k, base, room, X, Xc, best, bu);
                 }
-                const bool fast = ((ma + kGroup - 1) << k) + L.base + ((int64_t)umax << k) <= A.n_in;
-                // sliding window y_j[m0 + u4 .. m0 + u4 + 8) over blocks of 4 unit counts
-                float4 wa = *reinterpret_cast<const float4 *>(yj + m0);
-                for (int u4 = 0; u4 < umax; u4 += 4) {
-                    const float4 wb = *reinterpret_cast<const float4 *>(yj + m0 + u4 + 4);
-                    const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int u = u4 + t;
-                        if (u >= umax) break;
-#pragma unroll
-                        for (int q = 0; q < kGroup; ++q) X[q] += w[q + t];
-                        if ((emask >> u) & 1ull) {
-                            const float r = lds[L.lds_r + u];
-                            const int Lw = L.base + ((u + 1) << k);
-#pragma unroll
-                            for (int q = 0; q < kGroup; ++q) {
-                                float v = X[q] * r;
-                                if (!fast && Lw > room[q]) v = SPD_NEG_INF;
-                                if (v > best[q]) {
-                                    best[q] = v;
-                                    bw[q] = Lw;
-                                }
-                            }
-                        }
-                        if (pass_carry && u + 1 == L.ufull) {
-                            // this level's longest boxcar is the next level's carried prefix
-                            if (cn_lds) {
-                                cn_lds[(m0 >> 1) + 0] = X[0];
-                                cn_lds[(m0 >> 1) + 1] = X[2];
-                            } else if (cn_glb) {
-                                cn_glb[(m0 >> 1) + 0] = X[0];
-                                cn_glb[(m0 >> 1) + 1] = X[2];
-                            }
-                        }
-                    }
-                    wa = wb;
+                if (cn) {
+                    // this level's longest boxcar is the next level's carried prefix
+                    cn[(m0 >> 1) + 0] = Xc[0];
+                    cn[(m0 >> 1) + 1] = Xc[2];
                 }
-                float *Yr = A.Y + L.plane_off + (int64_t)d * L.pitch + ma;
-                uint16_t *Wr = A.W + L.plane_off + (int64_t)d * L.pitch + ma;
+                int bw[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) bw[q] = bu[q] ? base + (bu[q] << k) : 0;
                 if (ma + kGroup <= L.slots) {
-                    *reinterpret_cast<float4 *>(Yr) = make_float4(best[0], best[1], best[2], best[3]);
-                    *reinterpret_cast<uint2 *>(Wr) =
+                    *reinterpret_cast<float4 *>(rowY + ma) = make_float4(best[0], best[1], best[2], best[3]);
+                    *reinterpret_cast<uint2 *>(rowW + ma) =
                         make_uint2((uint32_t)bw[0] | ((uint32_t)bw[1] << 16),
                                    (uint32_t)bw[2] | ((uint32_t)bw[3] << 16));
                 } else {
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q)
                         if (ma + q < L.slots) {
-                            Yr[q] = best[q];
-                            Wr[q] = (uint16_t)bw[q];
+                            rowY[ma + q] = best[q];
+                            rowW[ma + q] = (uint16_t)bw[q];
                         }
                 }
             }
             if (A.want_cand) {
-                // time neighbours: inside the group, or the adjacent groups of the neighbouring
-                // lanes; unknown neighbours (wave edges) are treated as -inf (conservative)
-                float left = __shfl_up(best[kGroup - 1], 1);
-                float right = __shfl_down(best[0], 1);
-                if (lane == 0) left = SPD_NEG_INF;
-                if (lane == 63) right = SPD_NEG_INF;
-                int nh = 0;
-                bool hit[kGroup];
-#pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    const float l = q > 0 ? best[q - 1] : left;
-                    const float rr = q + 1 < kGroup ? best[q + 1] : right;
-                    hit[q] = act && (ma + q < L.slots) && best[q] > A.threshold && best[q] > l &&
-                             best[q] >= rr;
-                    nh += hit[q];
-                }
-                if (nh) {
-                    uint32_t pos = atomicAdd(&st_cnt[j], (uint32_t)nh);
+                const float gmax = fmaxf(fmaxf(best[0], best[1]), fmaxf(best[2], best[3]));
+                if (__ballot(gmax > A.threshold)) {
+                    // time neighbours: inside the group, or the adjacent groups of the
+                    // neighbouring lanes; unknown neighbours (wave edges) count as -inf
+                    float left = __shfl_up(best[kGroup - 1], 1);
+                    float right = __shfl_down(best[0], 1);
+                    if (lane == 0) left = SPD_NEG_INF;
+                    if (lane == 63) right = SPD_NEG_INF;
+                    int nh = 0;
+                    bool hit[kGroup];
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q) {
-                        if (hit[q]) {
-                            if (pos < (uint32_t)kSlabCap)
-                                A.slab_ent[slab * kSlabCap + pos] = (uint32_t)(ma + q);
-                            ++pos;
+                        const float l = q > 0 ? best[q - 1] : left;
+                        const float rr = q + 1 < kGroup ? best[q + 1] : right;
+                        hit[q] = act && (ma + q < L.slots) && best[q] > A.threshold &&
+                                 best[q] > l && best[q] >= rr;
+                        nh += hit[q];
+                    }
+                    if (nh) {
+                        const int64_t slab = L.slab_base + (int64_t)d * A.n_tiles + tile;
+                        uint32_t pos = atomicAdd(&st_cnt[j], (uint32_t)nh);
+#pragma unroll
+                        for (int q = 0; q < kGroup; ++q) {
+                            if (hit[q]) {
+                                if (pos < (uint32_t)kSlabCap)
+                                    A.slab_ent[slab * kSlabCap + pos] = (uint32_t)(ma + q);
+                                ++pos;
+                            }
                         }
                     }
                 }
@@ -697,10 +785,43 @@ int launch_evalmask(const MaskArgs &a, void *stream) {
     return (int)hipGetLastError();
 }
 
-int launch_step(const StepArgs &a, int lds_bytes, void *stream) {
+template <bool FIRST>
+static void launch_step_fam(const StepArgs &a, int fam, dim3 grid, int lds_bytes, hipStream_t st) {
+    const dim3 block(kStepThreads);
+    switch (fam) {
+        case 1: hipLaunchKernelGGL((step_kernel<FIRST, 1>), grid, block, lds_bytes, st, a); break;
+        case 2: hipLaunchKernelGGL((step_kernel<FIRST, 2>), grid, block, lds_bytes, st, a); break;
+        case 3: hipLaunchKernelGGL((step_kernel<FIRST, 3>), grid, block, lds_bytes, st, a); break;
+        case 4: hipLaunchKernelGGL((step_kernel<FIRST, 4>), grid, block, lds_bytes, st, a); break;
+        case 5: hipLaunchKernelGGL((step_kernel<FIRST, 5>), grid, block, lds_bytes, st, a); break;
+        case 6: hipLaunchKernelGGL((step_kernel<FIRST, 6>), grid, block, lds_bytes, st, a); break;
+        case 7: hipLaunchKernelGGL((step_kernel<FIRST, 7>), grid, block, lds_bytes, st, a); break;
+        default: hipLaunchKernelGGL((step_kernel<FIRST, 0>), grid, block, lds_bytes, st, a); break;
+    }
+}
+
+int launch_step(const StepArgs &a, int fam, int lds_bytes, void *stream) {
+    // the first step (raw samples, normalised on load) and the later steps (decimated series)
+    // are separate instantiations, so profiles tell them apart
     const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_tiles));
-    hipLaunchKernelGGL(step_kernel, grid, dim3(kStepThreads), lds_bytes, (hipStream_t)stream, a);
+    if (a.normalise)
+        launch_step_fam<true>(a, fam, grid, lds_bytes, (hipStream_t)stream);
+    else
+        launch_step_fam<false>(a, fam, grid, lds_bytes, (hipStream_t)stream);
     return (int)hipGetLastError();
+}
+
+uint64_t family_mask(int fam, int pattern) {
+    switch (fam) {
+        case 1: return pattern == 1 ? Fam<1>::M1 : Fam<1>::M2;
+        case 2: return pattern == 1 ? Fam<2>::M1 : Fam<2>::M2;
+        case 3: return pattern == 1 ? Fam<3>::M1 : Fam<3>::M2;
+        case 4: return Fam<4>::M1;
+        case 5: return Fam<5>::M1;
+        case 6: return Fam<6>::M1;
+        case 7: return Fam<7>::M1;
+        default: return 0;
+    }
 }
 
 int launch_exhaustive(const ExhArgs &a, bool dense, void *stream) {
