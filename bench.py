@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--no-loss", action="store_true", help="skip the noise-free twin loss")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample time")
+    ap.add_argument("--segment", type=int, default=0, help="tile length override (0: library's)")
     ap.add_argument("--profile-probe", action="store_true")
     args = ap.parse_args()
 
@@ -115,7 +116,7 @@ def main():
     sg = torch.ones(w.n_dm, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
-    cfg = spd.Config(args.method, w.l_end, threshold=w.threshold)
+    cfg = spd.Config(args.method, w.l_end, threshold=w.threshold, segment=args.segment)
     run = spd.Runner(x, mu, sg, cfg, cand_cap=1 << 22)
     info = run.info
 
@@ -274,6 +275,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "method": args.method, "n_dm": w.n_dm, "n_samples": w.n,
+                   "tile": info.segment,
                    "l_end": w.l_end, "threshold": w.threshold, "t_sample_us": 64,
                    "outputs": "planes+candidates", "pulses": len(w.pulses)},
         "rtf": rtf,

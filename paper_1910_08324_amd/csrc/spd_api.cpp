@@ -211,10 +211,13 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
         if (j < J) need = (T >> j) + s.levels[k0 + j].units.back() - 1;
         else need = T >> J;
         if (j < top) need = std::max<int64_t>(need, 2 * N[j + 1] + s.levels[k0 + j + 1].cshift);
-        N[j] = round_up(need, 4);
+        N[j] = j == 0 ? round_up(need, 4) : need;          // the window is loaded as float4
     }
-    int lds = 0;
+    // Levels alternate between two buffers: level j+1 is formed into the buffer level j-1 used
+    // (after level j-1's boxcars are done), so the tile needs only two level buffers and two
+    // carry buffers.
     int64_t capv[spd::kStepMaxLevels + 1] = {0};
+    int64_t ybuf[2] = {0, 0}, cbuf[2] = {0, 0};
     for (int j = 0; j <= top; ++j) {
         spd::StepLevel &L = st->lv[j];
         std::memset(&L, 0, sizeof(L));
@@ -222,11 +225,8 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
         L.k = lv.shift;
         L.cshift = j == 0 ? 0 : lv.cshift;
         L.n_units = (int)N[j];
-        const int64_t cap = (j < J) ? round_up(std::max<int64_t>(N[j], (T >> j) + st->maxu + 8), 4)
-                                    : N[j];
-        L.lds_y = lds;
-        capv[j] = cap;
-        lds += (int)cap;
+        capv[j] = round_up((j < J) ? std::max<int64_t>(N[j], (T >> j) + st->maxu + 8) : N[j], 4);
+        ybuf[j & 1] = std::max(ybuf[j & 1], capv[j]);
         L.base = lv.base;
         if (j < J) {
             L.umax = lv.units.back();
@@ -237,14 +237,23 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
             // 1/sqrt(L) for every unit count of the level, rounded once from FP64
             for (int u = 1; u <= L.umax; ++u)
                 st->rtab[j][u - 1] = (float)(1.0 / std::sqrt((double)lv.base + std::ldexp((double)u, lv.shift)));
+            if (s.method == SPD_BOXDIT && !(j == 0 && k0 == 0))
+                cbuf[j & 1] = std::max<int64_t>(cbuf[j & 1], round_up(T >> j, 4));
         }
     }
-    if (s.method == SPD_BOXDIT) {
-        for (int j = 0; j < J; ++j) {
-            if (j == 0 && k0 == 0) continue;
-            st->lv[j].lds_c = lds;
-            lds += T >> j;
-        }
+    int lds = 0;
+    const int y0 = lds;
+    lds += (int)ybuf[0];
+    const int y1 = lds;
+    lds += (int)ybuf[1];
+    const int c0 = lds;
+    lds += (int)cbuf[0];
+    const int c1 = lds;
+    lds += (int)cbuf[1];
+    for (int j = 0; j <= top; ++j) {
+        st->lv[j].lds_y = (j & 1) ? y1 : y0;
+        st->lv[j].lds_c = (j & 1) ? c1 : c0;
+        capv[j] = ybuf[j & 1];
     }
     st->lds_bytes = lds * 4;
     // a halo longer than the tile means the tile is too short for these levels

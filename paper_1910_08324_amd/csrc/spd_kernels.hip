@@ -18,6 +18,14 @@ namespace spd {
 
 #define SPD_NEG_INF (-__builtin_huge_valf())
 
+// Work-group barrier that orders LDS only: global loads and stores stay in flight across it
+// (a full __syncthreads() also waits for every outstanding global access of the wave).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ uint64_t lanes_below(int lane) {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
     const int64_t u0 = (int64_t)tile * T;
     if (tid < kStepMaxLevels) st_cnt[tid] = 0;
 
-    // ---- 1. window of the input series (and the first level's carried prefixes)
+    // ---- 1. window of the input series (normalised in the first step) and carried prefixes
     {
         const float *inr = A.in + (int64_t)d * A.ld_in;
         float mu = 0.0f, inv = 1.0f;
@@ -219,11 +227,12 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 
-    // ---- 2. decimation cascade
+    // ---- 2+3. cascade interleaved with the width sets: level j+1 is formed (into the buffer that
+    // level j-1 used) before level j's boxcars are evaluated, so only two level buffers are live
     const int jtop = A.has_out ? A.J : A.J - 1;
-    for (int j = 1; j <= jtop; ++j) {
+    auto form_level = [&](int j) {
         const float *yp = lds + A.lv[j - 1].lds_y + A.lv[j].cshift;
         float *yq = lds + A.lv[j].lds_y;
         const int nq = A.lv[j].n_units;
@@ -231,11 +240,12 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
             const float2 p = *reinterpret_cast<const float2 *>(yp + 2 * n);
             yq[n] = p.x + p.y;
         }
-        __syncthreads();
-    }
-
-    // ---- 3. width sets of every level
+    };
     for (int j = 0; j < A.J; ++j) {
+        if (j + 1 <= jtop) {
+            form_level(j + 1);
+            lds_barrier();
+        }
         const StepLevel &L = A.lv[j];
         const int Sj = T >> j;
         const int ms0 = tile * Sj;                         // absolute slot of tile slot 0
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
                 }
             }
         }
-        if (A.carry) __syncthreads();
+        lds_barrier();                       // level j's buffer is reused by level j+2
     }
 
     // ---- 4. hand on the last formed level
@@ -354,7 +364,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
         for (int n = tid; n < (T >> A.J); n += kStepThreads) o[n] = yJ[n];
     }
     if (A.want_cand) {
-        __syncthreads();
+        lds_barrier();
         if (tid < A.J) A.slab_cnt[A.lv[tid].slab_base + (int64_t)d * A.n_tiles + tile] = st_cnt[tid];
     }
 }
@@ -785,30 +795,32 @@ int launch_evalmask(const MaskArgs &a, void *stream) {
     return (int)hipGetLastError();
 }
 
+template <bool FIRST, int FAM>
+static int launch_one(const StepArgs &a, int lds_bytes, hipStream_t st) {
+    const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_tiles));
+    hipLaunchKernelGGL((step_kernel<FIRST, FAM>), grid, dim3(kStepThreads), lds_bytes, st, a);
+    return (int)hipGetLastError();
+}
+
 template <bool FIRST>
-static void launch_step_fam(const StepArgs &a, int fam, dim3 grid, int lds_bytes, hipStream_t st) {
-    const dim3 block(kStepThreads);
+static int launch_step_fam(const StepArgs &a, int fam, int lds_bytes, hipStream_t st) {
     switch (fam) {
-        case 1: hipLaunchKernelGGL((step_kernel<FIRST, 1>), grid, block, lds_bytes, st, a); break;
-        case 2: hipLaunchKernelGGL((step_kernel<FIRST, 2>), grid, block, lds_bytes, st, a); break;
-        case 3: hipLaunchKernelGGL((step_kernel<FIRST, 3>), grid, block, lds_bytes, st, a); break;
-        case 4: hipLaunchKernelGGL((step_kernel<FIRST, 4>), grid, block, lds_bytes, st, a); break;
-        case 5: hipLaunchKernelGGL((step_kernel<FIRST, 5>), grid, block, lds_bytes, st, a); break;
-        case 6: hipLaunchKernelGGL((step_kernel<FIRST, 6>), grid, block, lds_bytes, st, a); break;
-        case 7: hipLaunchKernelGGL((step_kernel<FIRST, 7>), grid, block, lds_bytes, st, a); break;
-        default: hipLaunchKernelGGL((step_kernel<FIRST, 0>), grid, block, lds_bytes, st, a); break;
+        case 1: return launch_one<FIRST, 1>(a, lds_bytes, st);
+        case 2: return launch_one<FIRST, 2>(a, lds_bytes, st);
+        case 3: return launch_one<FIRST, 3>(a, lds_bytes, st);
+        case 4: return launch_one<FIRST, 4>(a, lds_bytes, st);
+        case 5: return launch_one<FIRST, 5>(a, lds_bytes, st);
+        case 6: return launch_one<FIRST, 6>(a, lds_bytes, st);
+        case 7: return launch_one<FIRST, 7>(a, lds_bytes, st);
+        default: return launch_one<FIRST, 0>(a, lds_bytes, st);
     }
 }
 
 int launch_step(const StepArgs &a, int fam, int lds_bytes, void *stream) {
     // the first step (raw samples, normalised on load) and the later steps (decimated series)
     // are separate instantiations, so profiles tell them apart
-    const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_tiles));
-    if (a.normalise)
-        launch_step_fam<true>(a, fam, grid, lds_bytes, (hipStream_t)stream);
-    else
-        launch_step_fam<false>(a, fam, grid, lds_bytes, (hipStream_t)stream);
-    return (int)hipGetLastError();
+    if (a.normalise) return launch_step_fam<true>(a, fam, lds_bytes, (hipStream_t)stream);
+    return launch_step_fam<false>(a, fam, lds_bytes, (hipStream_t)stream);
 }
 
 uint64_t family_mask(int fam, int pattern) {

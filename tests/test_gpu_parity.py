@@ -125,7 +125,7 @@ def test_t0_offsets_candidate_starts(dev, method):
     assert np.array_equal(C1["snr"], C0["snr"]) and np.array_equal(C1["width"], C0["width"])
 
 
-@pytest.mark.parametrize("method,segs", [("ig1", [256, 1024, 8192]), ("bd16", [1024, 2048]),
+@pytest.mark.parametrize("method,segs", [("ig1", [256, 1024, 2048]), ("bd16", [1024, 2048]),
                                          ("ig3", [512, 3072]), ("bd32", [1024, 2048])])
 def test_tile_invariance_bitwise(dev, method, segs):
     """Results do not depend on how time is split into work items (bit for bit)."""
