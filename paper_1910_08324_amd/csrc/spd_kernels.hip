@@ -229,23 +229,15 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
     }
     lds_barrier();
 
-    // ---- 2+3. cascade interleaved with the width sets: level j+1 is formed (into the buffer that
-    // level j-1 used) before level j's boxcars are evaluated, so only two level buffers are live
+    // ---- 2+3. cascade fused with the width sets: while level j's boxcars are evaluated, each
+    // group also forms level j+1's units from its window (into the buffer level j-1 used), so a
+    // level costs one pass over LDS and one barrier, and only two level buffers are live.
     const int jtop = A.has_out ? A.J : A.J - 1;
-    auto form_level = [&](int j) {
-        const float *yp = lds + A.lv[j - 1].lds_y + A.lv[j].cshift;
-        float *yq = lds + A.lv[j].lds_y;
-        const int nq = A.lv[j].n_units;
-        for (int n = tid; n < nq; n += kStepThreads) {
-            const float2 p = *reinterpret_cast<const float2 *>(yp + 2 * n);
-            yq[n] = p.x + p.y;
-        }
-    };
     for (int j = 0; j < A.J; ++j) {
-        if (j + 1 <= jtop) {
-            form_level(j + 1);
-            lds_barrier();
-        }
+        const bool form_next = j + 1 <= jtop;
+        float *yn = form_next ? lds + A.lv[j + 1].lds_y : nullptr;
+        const int cs1 = form_next ? A.lv[j + 1].cshift : 0;
+        const int n_next = form_next ? A.lv[j + 1].n_units : 0;
         const StepLevel &L = A.lv[j];
         const int Sj = T >> j;
         const int ms0 = tile * Sj;                         // absolute slot of tile slot 0
@@ -278,6 +270,13 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
             for (int q = 0; q < kGroup; ++q) {
                 best[q] = SPD_NEG_INF;
                 bu[q] = 0;
+            }
+            if (form_next && g < ngroups) {
+                // y_{j+1}[n] = y_j[2n + cshift] + y_j[2n + cshift + 1] for 2n + cshift = m0, m0 + 2
+                const float4 w0 = *reinterpret_cast<const float4 *>(yj + m0);
+                const int n0 = (m0 - cs1) >> 1;
+                if (n0 >= 0 && n0 < n_next) yn[n0] = w0.x + w0.y;
+                if (n0 + 1 >= 0 && n0 + 1 < n_next) yn[n0 + 1] = w0.z + w0.w;
             }
             if (act) {
                 float X[kGroup], Xc[kGroup];
@@ -354,7 +353,14 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
                 }
             }
         }
-        lds_barrier();                       // level j's buffer is reused by level j+2
+        if (form_next) {
+            // units of level j+1 beyond the tile's slots (its halo)
+            for (int n = max(0, (Sj - cs1) >> 1) + tid; n < n_next; n += kStepThreads) {
+                const float2 p = *reinterpret_cast<const float2 *>(yj + 2 * n + cs1);
+                yn[n] = p.x + p.y;
+            }
+        }
+        lds_barrier();                       // level j+1 is complete; level j's buffer is reused
     }
 
     // ---- 4. hand on the last formed level
@@ -384,6 +390,39 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
 // ----------------------------------------------------------------------------------------
 __device__ __forceinline__ float load_z(const float *xr, int r, int n_in, float mu, float inv) {
     return r < n_in ? (xr[r] - mu) * inv : 0.0f;
+}
+
+// 64 widths L0 .. L0+63 at the lane's 4 starts: running sums X, group maxima gm.  The window
+// z[s0 + 4 lane + L0 - 1 ..] is read from the LDS ring one float4 per 4 widths.
+template <bool CHECK, bool DENSE>
+__device__ __forceinline__ void exh_group(const float4 *ring4, int jb4, int L0, const float *scale,
+                                          const uint32_t *evalmask, int Lw, const int room[4],
+                                          float X[4], float gm[4]) {
+    float4 wa = ring4[jb4 & 511];
+#pragma unroll 4
+    for (int t = 0; t < kExhGroup / 4; ++t) {
+        const float4 wb = ring4[(jb4 + t + 1) & 511];
+        const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+        const int L = L0 + 4 * t;
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            const float r = scale[L - 1 + tt];
+            bool on = true;
+            if (!DENSE) on = (evalmask[(L - 1 + tt) >> 5] >> ((L - 1 + tt) & 31)) & 1u;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                X[v] += w[v + tt];
+                float snr = X[v] * r;
+                if (CHECK) {
+                    const bool ok = (L + tt <= Lw) && (L + tt <= room[v]);
+                    snr = ok ? snr : SPD_NEG_INF;
+                }
+                if (!DENSE) snr = on ? snr : SPD_NEG_INF;
+                gm[v] = fmaxf(gm[v], snr);
+            }
+        }
+        wa = wb;
+    }
 }
 
 template <bool DENSE>
@@ -446,6 +485,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
         for (int gi = 0; gi < kExhBlock / kExhGroup; ++gi) {
             const int L0 = b * kExhBlock + gi * kExhGroup + 1;
             if (L0 > Lw) break;
+            // wave-uniform: every width of the group fits at every start of the work item
             const bool fast = (L0 + kExhGroup - 1 <= Lw) &&
                               ((int64_t)s0 + kExhSlots - 1 + L0 + kExhGroup - 1 <= n_in);
             float Xs[4], gm[4];
@@ -455,31 +495,10 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
                 gm[v] = SPD_NEG_INF;
             }
             const int jb4 = lane + ((L0 - 1) >> 2);
-            float4 wa = ring4[jb4 & 511];
-#pragma unroll 4
-            for (int t = 0; t < kExhGroup / 4; ++t) {
-                const float4 wb = ring4[(jb4 + t + 1) & 511];
-                const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-                const int L = L0 + 4 * t;
-#pragma unroll
-                for (int tt = 0; tt < 4; ++tt) {
-                    const float r = A.scale[L - 1 + tt];
-                    bool on = true;
-                    if (!DENSE) on = (A.evalmask[(L - 1 + tt) >> 5] >> ((L - 1 + tt) & 31)) & 1u;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        X[v] += w[v + tt];
-                        float snr = X[v] * r;
-                        if (!fast) {
-                            const bool ok = (L + tt <= Lw) && (L + tt <= room[v]);
-                            snr = ok ? snr : SPD_NEG_INF;
-                        }
-                        if (!DENSE) snr = on ? snr : SPD_NEG_INF;
-                        gm[v] = fmaxf(gm[v], snr);
-                    }
-                }
-                wa = wb;
-            }
+            if (fast)
+                exh_group<false, DENSE>(ring4, jb4, L0, A.scale, A.evalmask, Lw, room, X, gm);
+            else
+                exh_group<true, DENSE>(ring4, jb4, L0, A.scale, A.evalmask, Lw, room, X, gm);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 if (gm[v] > best[v]) {

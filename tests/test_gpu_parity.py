@@ -239,3 +239,23 @@ def test_small_exhaustive_workload_full(dev):
         say(f"  candidates={nc} robust={nr} pulses recovered {found}/{len(w.pulses)}")
         if method == "exh":
             assert found == len(w.pulses)
+
+
+@pytest.mark.parametrize("cfgkw,levels", [
+    (dict(method="bd", boxdit_lmax=[16, 8, 4, 32]), lambda L: ow.boxdit_levels([16, 8, 4, 32], L)),
+    (dict(method="bd", boxdit_lmax=[6]), lambda L: ow.boxdit_levels([6], L)),
+    (dict(method="ig", igrid_depth=4, igrid_layers=32), lambda L: ow.igrid_levels(4, L, layers=32)),
+    (dict(method="ig", igrid_depth=1, igrid_layers=8), lambda L: ow.igrid_levels(1, L, layers=8)),
+    (dict(method="ig", igrid_depth=2, igrid_layers=4), lambda L: ow.igrid_levels(2, L, layers=4)),
+])
+def test_generic_width_sets(dev, cfgkw, levels):
+    """Width sets outside the compiled-in families run through the generic bank path."""
+    from paper_1910_08324_amd import spd
+    x, mu, sg = make_input(4, 30011, 21, pulses=[synth.Pulse(1, 4000, 900, 20.0, "gauss"),
+                                                   synth.Pulse(2, 9000, 17, 12.0)])
+    l_end = 3000
+    cfg = spd.Config(l_end=l_end, threshold=4.0, **cfgkw)
+    P, C, res = run(dev, x, mu, sg, cfg)
+    R = oplanes.planes(x, mu, sg, levels(l_end))
+    parity.check_planes(P, R, x, mu, sg, 30011, what=str(cfgkw))
+    parity.check_candidates(C, R, 4.0, what=str(cfgkw))
