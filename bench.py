@@ -35,6 +35,9 @@ sys.path.insert(0, ROOT)
 METRIC = "DM·samples/s and real-time factor vs exhaustive at ≤7% mean power loss"
 T_SAMPLE = 64e-6             # sampling time of the workload (s)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E peak
+# FP32 vector peak 157.3 TFLOP/s counts an FMA as 2 operations: 256 FLOP per clock per CU on
+# 256 CUs at 2.4 GHz, i.e. 128 single-operation lanes per clock per CU.
+VALU_PEAK_TOPS = 128 * 256 * 2.4e9 / 1e12
 KERNEL_SRC = os.path.join(ROOT, "paper_1910_08324_amd", "csrc", "spd_kernels.hip")
 PMC_FILE = os.path.join(ROOT, "profiles", "lossy_kernel_ska_beam_counters.txt")
 
@@ -49,26 +52,94 @@ def kernel_source_hash() -> str:
 
 
 def algorithmic_bytes(info, n_dm: int, n_in: int) -> int:
-    """Bytes the filter must move per launch: read every input sample once (4 B) and write
-    every plane slot once (4 B SNR + 2 B width)."""
+    """Bytes a whole filter pass must move: read every input sample once (4 B) and write every
+    plane slot once (4 B SNR + 2 B width)."""
     slots = sum(int(info.plane_slots[i]) for i in range(info.n_levels))
     return n_dm * n_in * 4 + n_dm * slots * 6
 
 
-def read_traffic(method: str):
-    """HBM traffic per launch from the committed counter summary, if it was taken on the
-    current kernel source; else None."""
+def launch_bytes(info, i: int, n_dm: int) -> int:
+    """Algorithmic bytes of filter launch i: the floats it reads per row once (the samples, or the
+    decimated series handed on by the previous launch), the plane slots of its levels once
+    (6 B each) and the floats it hands to the next launch once."""
+    b = n_dm * 4 * (int(info.launch_in_units[i]) + int(info.launch_out_units[i]))
+    f, c = int(info.launch_first_level[i]), int(info.launch_levels[i])
+    if f >= 0:
+        b += n_dm * 6 * sum(int(info.plane_slots[k]) for k in range(f, f + c))
+    return b
+
+
+FAMILY = {"ig1": 1, "ig2": 2, "ig3": 3, "bd8": 4, "bd16": 5, "bd32": 6, "dit": 7}
+
+
+def launch_kernel_name(method: str, info, i: int) -> str:
+    """Kernel symbol of filter launch i, as rocprofv3 lists it."""
+    if method == "exh":
+        return "spd::exh_kernel<true>" if info.launch_first_level[i] >= 0 else "spd::scales_kernel"
+    first = "true" if info.launch_first_level[i] == 0 else "false"
+    return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}>"
+
+
+def launch_valu_ops(method: str, cfg, info, i: int, n_dm: int, n_in: int) -> float:
+    """Algorithmic FP32 lane operations of filter launch i.  Lossy levels: per slot one add per
+    unit of the widest boxcar (running sums) plus multiply, max and width select per width;
+    the exhaustive set: add, multiply and max per (start, width) pair that fits."""
+    f, c = int(info.launch_first_level[i]), int(info.launch_levels[i])
+    if f < 0:
+        return 0.0
+    if method == "exh":
+        L = min(cfg.l_end, n_in)
+        n_out = int(info.plane_slots[0])
+        pairs = n_out * L - max(0, n_out + L - 1 - n_in) * (n_out + L - n_in) / 2
+        return 3.0 * n_dm * pairs
+    from paper_1910_08324_amd import spd
+    lw = spd.level_widths(cfg)
+    ops = 0.0
+    for k in range(f, f + c):
+        ws, sh = lw[k], int(info.level_shift[k])
+        umax = (ws[-1] - ws[0]) // (1 << sh) + 1
+        ops += n_dm * int(info.plane_slots[k]) * (umax + 3 * len(ws))
+    return ops
+
+
+def time_launches(run, reps: int):
+    """Average duration (ms) of each filter launch, from HIP events recorded around each launch
+    on the runner's stream by the library (spd_filter_timed)."""
+    import numpy as np
+    t = np.array([run.filter_timed() for _ in range(reps)])
+    return [float(v) for v in t.mean(axis=0)]
+
+
+def dominant_entry(method: str, cfg, run, w, reps: int, lms=None) -> dict:
+    """The longest filter launch of a method with its HBM and VALU fractions of peak."""
+    info = run.info
+    if lms is None:
+        lms = time_launches(run, reps)
+    dom = max(range(len(lms)), key=lambda i: lms[i])
+    sec = lms[dom] * 1e-3
+    gbs = launch_bytes(info, dom, w.n_dm) / sec / 1e9
+    tops = launch_valu_ops(method, cfg, info, dom, w.n_dm, w.n) / sec / 1e12
+    hf, vf = gbs / HBM_PEAK_GBS, tops / VALU_PEAK_TOPS
+    return {"kernel": launch_kernel_name(method, info, dom), "ms": round(lms[dom], 4),
+            "launch_ms": [round(v, 4) for v in lms], "gbs": round(gbs, 1),
+            "hbm_frac": round(hf, 4), "valu_tops": round(tops, 2), "valu_frac": round(vf, 4),
+            "bound": "hbm" if hf >= vf else "alu"}
+
+
+def read_traffic(method: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on
+    the current kernel source for this method; else None."""
     if not os.path.exists(PMC_FILE):
         return None
     vals = {}
     with open(PMC_FILE) as f:
         for line in f:
-            if ":" in line and not line.startswith("#"):
+            if ":" in line and not line.startswith("#") and "|" not in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    if vals.get("method") != method:
+    if vals.get("method") != method or vals.get("kernel") != kernel:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -128,9 +199,13 @@ def main():
         y = torch.empty_like(x)
         torch.mul(x, 1.0, out=y)            # plain streaming kernel: reads and writes copy_bytes
         torch.cuda.synchronize()
+        launches = [{"kernel": launch_kernel_name(args.method, info, i),
+                     "algorithmic_bytes": launch_bytes(info, i, w.n_dm)}
+                    for i in range(info.n_launches)]
         print(json.dumps({"probe": "ok", "method": args.method, "search_launches": 4,
                           "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes,
-                          "algorithmic_bytes_per_launch": algorithmic_bytes(info, w.n_dm, w.n),
+                          "launches": launches,
+                          "algorithmic_bytes_filter": algorithmic_bytes(info, w.n_dm, w.n),
                           "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
         return
 
@@ -159,13 +234,30 @@ def main():
     log(f"[bench] {args.method}: {ms_step:.3f} ms/step (filter {filt_ms:.3f} ms, peaks "
         f"{peak_ms:.3f} ms), {value:.3e} DM*samples/s, RTF {rtf:.0f}, candidates {n_cand}")
 
-    abytes = algorithmic_bytes(info, w.n_dm, w.n)
-    achieved = abytes / (filt_ms * 1e-3) / 1e9
-    traffic = read_traffic(args.method)
-    roofline = {"bound": "hbm", "kernel": "lossy_kernel", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes_per_launch": abytes,
-                "kernel_ms": round(filt_ms, 4)}
+    # dominant kernel: the filter launch that takes longest, timed per launch with HIP events
+    lms = time_launches(run, K)
+    dom_main = dominant_entry(args.method, cfg, run, w, K, lms)
+    dom = lms.index(max(lms))
+    abytes = launch_bytes(info, dom, w.n_dm)
+    if dom_main["bound"] == "hbm":
+        achieved, peak, unit = dom_main["gbs"], HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = dom_main["valu_tops"], round(VALU_PEAK_TOPS, 2), "TFLOP/s"
+    roofline = {"bound": dom_main["bound"], "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4),
+                "traffic": read_traffic(args.method, dom_main["kernel"]),
+                "kernel": dom_main["kernel"],
+                "levels": [int(info.launch_first_level[dom]),
+                           int(info.launch_first_level[dom] + info.launch_levels[dom] - 1)],
+                "algorithmic_bytes_per_launch": abytes,
+                "algorithmic_valu_ops_per_launch": launch_valu_ops(args.method, cfg, info, dom,
+                                                                   w.n_dm, w.n),
+                "kernel_ms": dom_main["ms"], "launch_ms": dom_main["launch_ms"],
+                "hbm_frac": dom_main["hbm_frac"], "valu_frac": dom_main["valu_frac"],
+                "filter_gbs": round(algorithmic_bytes(info, w.n_dm, w.n) / (filt_ms * 1e-3) / 1e9, 1)}
+    log(f"[bench] dominant launch {dom} ({roofline['kernel']}): {dom_main['ms']:.3f} ms, "
+        f"{dom_main['gbs']:.0f} GB/s = {dom_main['hbm_frac']:.3f} of HBM peak, VALU "
+        f"{dom_main['valu_frac']:.3f} of peak")
 
     # recall of injected pulses among the candidates (noisy beam)
     C = run.result.candidates_host()
@@ -179,13 +271,14 @@ def main():
 
     # ---------------- other methods, exhaustive --------------------------------------------
     methods = {args.method: {"ms": round(ms_step, 4), "rtf": round(rtf, 1),
-                             "filter_ms": round(filt_ms, 4), "gbs": round(achieved, 1)}}
+                             "filter_ms": round(filt_ms, 4), "dominant": dom_main}}
     others = [] if args.no_methods else [m for m in ("ig1", "ig2", "ig3", "bd8", "bd16", "bd32")
                                          if m != args.method]
     if not args.no_exhaustive:
         others.append("exh")
     for m in others:
-        r = spd.Runner(x, mu, sg, spd.Config(m, w.l_end, threshold=w.threshold), cand_cap=1 << 22)
+        cfg_m = spd.Config(m, w.l_end, threshold=w.threshold)
+        r = spd.Runner(x, mu, sg, cfg_m, cand_cap=1 << 22)
         r.search()
         torch.cuda.synchronize()
         n_rep = args.exh_steps if m == "exh" else 5
@@ -206,10 +299,11 @@ def main():
         fms = tf / n_rep
         ent = {"ms": round(ms, 4), "rtf": round(w.n * T_SAMPLE / (ms * 1e-3), 2),
                "filter_ms": round(fms, 4)}
-        if m != "exh":
-            ent["gbs"] = round(algorithmic_bytes(r.info, w.n_dm, w.n) / (fms * 1e-3) / 1e9, 1)
+        ent["dominant"] = dominant_entry(m, cfg_m, r, w, n_rep)
         methods[m] = ent
-        log(f"[bench] {m}: {ms:.3f} ms/search (filter {fms:.3f} ms), RTF {ent['rtf']}")
+        log(f"[bench] {m}: {ms:.3f} ms/search (filter {fms:.3f} ms), RTF {ent['rtf']}, dominant "
+            f"{ent['dominant']['kernel']} {ent['dominant']['ms']} ms: "
+            f"HBM {ent['dominant']['hbm_frac']:.3f}, VALU {ent['dominant']['valu_frac']:.3f}")
         del r
         torch.cuda.empty_cache()
 

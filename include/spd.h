@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SPD_ABI_VERSION 1
+#define SPD_ABI_VERSION 2
 
 /* Status codes. */
 #define SPD_OK          0
@@ -63,6 +63,7 @@ extern "C" {
 #define SPD_MAX_LEVEL_WIDTHS 64   /* widths per level for BoxDIT and IGRID                     */
 #define SPD_MAX_LEND 65535        /* widths are stored as uint16                               */
 #define SPD_MAX_LIST_LEND 16384   /* largest width when an explicit exhaustive list is given   */
+#define SPD_MAX_LAUNCHES 26       /* kernel launches of one spd_filter call                    */
 
 /*
  * Search parameters.  All pointers in this struct are HOST pointers, read during the call only.
@@ -79,8 +80,9 @@ extern "C" {
  *   threshold       candidates need SNR strictly above it.
  *   flags           SPD_WRITE_PLANES | SPD_WRITE_CANDIDATES.
  *   segment         samples per work item along time (0 = chosen by the library).  Results do not
- *                   depend on it.  BoxDIT / IGRID: a multiple of 1024 and of 2^(K+2);
- *                   exhaustive: 256 only.
+ *                   depend on it.  BoxDIT / IGRID: a multiple of 256 in 256..32768 that leaves
+ *                   every launch of the level cascade room for its halo and its on-chip buffers
+ *                   (spd_plan returns SPD_EINVAL otherwise); exhaustive: 256 only.
  */
 typedef struct {
     int32_t method;
@@ -121,6 +123,13 @@ typedef struct {
     int64_t workspace_bytes;                  /* device workspace spd_search needs              */
     int32_t segment;                          /* samples per work item along time              */
     int32_t n_segments;                       /* work items per DM row                          */
+    /* the kernel launches of spd_filter, in stream order (for measurement and accounting) */
+    int32_t n_launches;
+    int32_t launch_first_level[SPD_MAX_LAUNCHES]; /* first level computed; -1 for a set-up launch */
+    int32_t launch_levels[SPD_MAX_LAUNCHES];      /* levels computed (planes written)           */
+    int64_t launch_in_units[SPD_MAX_LAUNCHES];    /* floats read per DM row (samples, or decimated
+                                                     series and carried prefixes handed on)   */
+    int64_t launch_out_units[SPD_MAX_LAUNCHES];   /* floats per DM row handed to the next launch */
 } spd_plan_info;
 
 /*
@@ -170,8 +179,10 @@ int spd_search(const spd_params *params, const float *x, int64_t ld, int32_t n_d
  *
  * spd_filter: the boxcar search only (Sections 3.1 and 3.2): writes the planes (to snr/width,
  *   or into the workspace when SPD_WRITE_PLANES is not set) and, when SPD_WRITE_CANDIDATES is
- *   set, records in the workspace the slots above the threshold for spd_peaks.  For BoxDIT and
- *   IGRID it is a single kernel launch.  Arguments as for spd_search.
+ *   set, records in the workspace the slots above the threshold for spd_peaks.  BoxDIT and
+ *   IGRID run as a chain of cascade launches, each computing up to six levels on chip and
+ *   handing its last decimated series (and, for BoxDIT, the carried prefixes) to the next
+ *   through the workspace; spd_plan_info lists them.  Arguments as for spd_search.
  * spd_peaks: candidate selection from the planes and records left by spd_filter (params->flags
  *   must include SPD_WRITE_CANDIDATES; snr/width as given to spd_filter).  Arguments as for
  *   spd_search.
@@ -183,6 +194,20 @@ int spd_filter(const spd_params *params, const float *x, int64_t ld, int32_t n_d
 int spd_peaks(const spd_params *params, int32_t n_dm, int32_t n_in, int32_t n_out, int64_t t0,
               const float *snr, const uint16_t *width, spd_candidate *cand, int64_t cand_cap,
               int64_t *cand_count, void *workspace, int64_t workspace_bytes, void *hip_stream);
+
+/*
+ * spd_filter_timed: spd_filter with a HIP event recorded on `hip_stream` before the first kernel
+ *   launch and after each one.  It then waits for the last event and writes each launch's
+ *   duration in milliseconds to the HOST array launch_ms (at most `cap` entries, in the order of
+ *   spd_plan_info's launch list) and the number of launches to the HOST int *n_launches.  Meant
+ *   for measurement: unlike the other calls it creates and destroys HIP events and blocks the
+ *   calling thread until the filter has finished.  Returns as spd_filter, or SPD_EHIP if an
+ *   event call failed.
+ */
+int spd_filter_timed(const spd_params *params, const float *x, int64_t ld, int32_t n_dm,
+                     int32_t n_in, int32_t n_out, const float *mean, const float *sigma,
+                     float *snr, uint16_t *width, void *workspace, int64_t workspace_bytes,
+                     void *hip_stream, float *launch_ms, int32_t cap, int32_t *n_launches);
 
 /* Human-readable text for a status code (static storage; includes the last HIP error text for
  * SPD_EHIP on this thread). */

@@ -8,6 +8,8 @@
 #include <cstring>
 #include <vector>
 
+#include <hip/hip_runtime_api.h>
+
 #include "spd.h"
 #include "spd_internal.h"
 
@@ -213,11 +215,11 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
         if (j < top) need = std::max<int64_t>(need, 2 * N[j + 1] + s.levels[k0 + j + 1].cshift);
         N[j] = j == 0 ? round_up(need, 4) : need;          // the window is loaded as float4
     }
-    // Levels alternate between two buffers: level j+1 is formed into the buffer level j-1 used
-    // (after level j-1's boxcars are done), so the tile needs only two level buffers and two
-    // carry buffers.
+    // One unit buffer and one carry buffer per tile: level j+1 is written over the part of
+    // level j that the tile has finished with (the units a batch of groups has read), so the
+    // buffers only need to hold the largest level.
     int64_t capv[spd::kStepMaxLevels + 1] = {0};
-    int64_t ybuf[2] = {0, 0}, cbuf[2] = {0, 0};
+    int64_t ybuf = 0, cbuf = 0;
     for (int j = 0; j <= top; ++j) {
         spd::StepLevel &L = st->lv[j];
         std::memset(&L, 0, sizeof(L));
@@ -226,7 +228,7 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
         L.cshift = j == 0 ? 0 : lv.cshift;
         L.n_units = (int)N[j];
         capv[j] = round_up((j < J) ? std::max<int64_t>(N[j], (T >> j) + st->maxu + 8) : N[j], 4);
-        ybuf[j & 1] = std::max(ybuf[j & 1], capv[j]);
+        ybuf = std::max(ybuf, capv[j]);
         L.base = lv.base;
         if (j < J) {
             L.umax = lv.units.back();
@@ -238,24 +240,16 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
             for (int u = 1; u <= L.umax; ++u)
                 st->rtab[j][u - 1] = (float)(1.0 / std::sqrt((double)lv.base + std::ldexp((double)u, lv.shift)));
             if (s.method == SPD_BOXDIT && !(j == 0 && k0 == 0))
-                cbuf[j & 1] = std::max<int64_t>(cbuf[j & 1], round_up(T >> j, 4));
+                cbuf = std::max<int64_t>(cbuf, round_up(T >> j, 4));
         }
     }
-    int lds = 0;
-    const int y0 = lds;
-    lds += (int)ybuf[0];
-    const int y1 = lds;
-    lds += (int)ybuf[1];
-    const int c0 = lds;
-    lds += (int)cbuf[0];
-    const int c1 = lds;
-    lds += (int)cbuf[1];
     for (int j = 0; j <= top; ++j) {
-        st->lv[j].lds_y = (j & 1) ? y1 : y0;
-        st->lv[j].lds_c = (j & 1) ? c1 : c0;
-        capv[j] = ybuf[j & 1];
+        st->lv[j].lds_y = 0;
+        st->lv[j].lds_c = (int)ybuf;
+        capv[j] = ybuf;
     }
-    st->lds_bytes = lds * 4;
+    const int64_t lds = ybuf + cbuf;
+    st->lds_bytes = (int)(lds * 4);
     // a halo longer than the tile means the tile is too short for these levels
     if (N[0] - T > T) return -1;
     // every LDS read of the kernel must land on a unit the tile formed:
@@ -263,6 +257,14 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
     //   banks    y_j[m + u], m < T >> j, u < umax_j;  float4 window reads up to m + umax_j + 7
     for (int j = 1; j <= top; ++j)
         if (2 * (N[j] - 1) + st->lv[j].cshift + 1 >= N[j - 1]) return -1;
+    // in-place formation: the halo units of level j+1 (n >= (S_j - cshift) / 2, formed after
+    // the last batch of level j) are written below every unit of level j that they read
+    for (int j = 1; j <= top; ++j) {
+        const int64_t Sp = T >> (j - 1);
+        const int64_t cs = st->lv[j].cshift;
+        const int64_t n_start = std::max<int64_t>(0, (Sp - cs) >> 1);
+        if (N[j] > 2 * n_start + cs) return -1;
+    }
     for (int j = 0; j < J; ++j) {
         const int64_t last_used = (T >> j) - 1 + st->lv[j].umax - 1;
         const int64_t um = st->lv[j].umax;
@@ -370,6 +372,26 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
             }
         }
     }
+    // the launches of the filter, in stream order
+    auto add_launch = [&](int first, int nlv, int64_t in_units, int64_t out_units) {
+        const int i = I.n_launches++;
+        I.launch_first_level[i] = first;
+        I.launch_levels[i] = nlv;
+        I.launch_in_units[i] = in_units;
+        I.launch_out_units[i] = out_units;
+    };
+    if (lossy) {
+        const int series = s.method == SPD_BOXDIT ? 2 : 1;   // decimated series (+ carried prefixes)
+        for (const StepPlan &st : L->steps)
+            add_launch(st.k0, st.J, st.k0 == 0 ? (int64_t)n_in : series * st.in_len,
+                       st.has_out ? series * st.out_len : 0);
+    } else {
+        add_launch(-1, 0, 0, 0);                                  // 1/sqrt(L) table
+        if (!s.dense) add_launch(-1, 0, 0, 0);                    // width mask
+        add_launch(0, 1, n_in, 0);
+    }
+    if (I.n_launches > SPD_MAX_LAUNCHES) return SPD_EINVAL;
+
     L->slab_base[0] = 0;
     for (int k = 0; k < nlev; ++k)
         L->slab_base[k + 1] = L->slab_base[k] + (int64_t)n_dm * L->tiles_per_row[k];
@@ -477,9 +499,27 @@ int prepare(const spd_params *params, int32_t n_dm, int32_t n_in, int32_t n_out,
     return SPD_OK;
 }
 
+// HIP events recorded before the first launch and after each launch (spd_filter_timed).
+struct LaunchMarks {
+    hipStream_t stream = nullptr;
+    std::vector<hipEvent_t> ev;
+    int mark() {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return (int)err;
+        ev.push_back(e);
+        return (int)hipEventRecord(e, stream);
+    }
+    ~LaunchMarks() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
 int run_filter(const spd_params *params, const Prepared &P, const float *x, int64_t ld,
                int32_t n_dm, int32_t n_in, int32_t n_out, const float *mean, const float *sigma,
-               void *hip_stream) {
+               void *hip_stream, LaunchMarks *marks = nullptr) {
+    auto mark = [&]() { return marks ? marks->mark() : 0; };
+    if (const int err = mark()) return hip_fail(err);
     const Search &s = P.s;
     const Layout &L = P.L;
     const spd_plan_info &I = L.info;
@@ -525,6 +565,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
             std::memcpy(a.rtab, st.rtab, sizeof(a.rtab));
             const int err = spd::launch_step(a, s.fam, st.lds_bytes, hip_stream);
             if (err) return hip_fail(err);
+            if (const int e2 = mark()) return hip_fail(e2);
             in = a.out;
             ld_in = st.ld_out;
             cin = a.cout;
@@ -539,6 +580,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
         a.n = L.n_scale;
         const int err = spd::launch_scales(a, hip_stream);
         if (err) return hip_fail(err);
+        if (const int e2 = mark()) return hip_fail(e2);
     }
     if (!s.dense) {
         spd::MaskArgs m;
@@ -548,6 +590,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
         for (int w : s.levels[0].widths) m.bits[(w - 1) >> 5] |= 1u << ((w - 1) & 31);
         const int err = spd::launch_evalmask(m, hip_stream);
         if (err) return hip_fail(err);
+        if (const int e2 = mark()) return hip_fail(e2);
     }
     spd::ExhArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -572,6 +615,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
     a.threshold = params->threshold;
     const int err = spd::launch_exhaustive(a, s.dense, hip_stream);
     if (err) return hip_fail(err);
+    if (const int e2 = mark()) return hip_fail(e2);
     return SPD_OK;
 }
 
@@ -626,6 +670,30 @@ int spd_filter(const spd_params *params, const float *x, int64_t ld, int32_t n_d
     if (st != SPD_OK) return st;
     if (!x || !mean || !sigma || ld < n_in) return SPD_EINVAL;
     return run_filter(params, P, x, ld, n_dm, n_in, n_out, mean, sigma, hip_stream);
+}
+
+int spd_filter_timed(const spd_params *params, const float *x, int64_t ld, int32_t n_dm,
+                     int32_t n_in, int32_t n_out, const float *mean, const float *sigma,
+                     float *snr, uint16_t *width, void *workspace, int64_t workspace_bytes,
+                     void *hip_stream, float *launch_ms, int32_t cap, int32_t *n_launches) {
+    if (!n_launches || cap < 0 || (cap > 0 && !launch_ms)) return SPD_EINVAL;
+    Prepared P;
+    int st = prepare(params, n_dm, n_in, n_out, snr, width, workspace, workspace_bytes, &P);
+    if (st != SPD_OK) return st;
+    if (!x || !mean || !sigma || ld < n_in) return SPD_EINVAL;
+    LaunchMarks marks;
+    marks.stream = static_cast<hipStream_t>(hip_stream);
+    st = run_filter(params, P, x, ld, n_dm, n_in, n_out, mean, sigma, hip_stream, &marks);
+    if (st != SPD_OK) return st;
+    const int n = (int)marks.ev.size() - 1;
+    hipError_t err = hipEventSynchronize(marks.ev.back());
+    if (err != hipSuccess) return hip_fail((int)err);
+    for (int i = 0; i < n && i < cap; ++i) {
+        err = hipEventElapsedTime(&launch_ms[i], marks.ev[i], marks.ev[i + 1]);
+        if (err != hipSuccess) return hip_fail((int)err);
+    }
+    *n_launches = n;
+    return SPD_OK;
 }
 
 int spd_peaks(const spd_params *params, int32_t n_dm, int32_t n_in, int32_t n_out, int64_t t0,

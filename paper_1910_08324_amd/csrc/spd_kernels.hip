@@ -83,22 +83,26 @@ __host__ __device__ constexpr uint64_t ig_mask_lk(int P, int d) {
 }
 __host__ __device__ constexpr uint64_t run_mask(int L) { return L >= 64 ? ~0ull : ((1ull << L) - 1); }
 
-// Compiled-in width patterns of each family: (UMAX, MASK) for pattern 1 and pattern 2.
+// Compiled-in width patterns of each family: (UMAX, MASK) for pattern 1 and pattern 2, and the
+// waves per SIMD the kernel is compiled for (register budget: 8 waves leave 64 VGPRs and 96
+// SGPRs per lane; IG(3)'s 30-unit window needs a few more VGPRs than that).
 template <int FAM> struct Fam;
-template <> struct Fam<0> { static constexpr int U1 = 1, U2 = 1; static constexpr uint64_t M1 = 1, M2 = 1; };
-template <> struct Fam<1> { static constexpr int U1 = 6, U2 = 6;
+template <> struct Fam<0> { static constexpr int U1 = 1, U2 = 1, WAVES = 7;
+                            static constexpr uint64_t M1 = 1, M2 = 1; };
+template <> struct Fam<1> { static constexpr int U1 = 6, U2 = 6, WAVES = 8;
                             static constexpr uint64_t M1 = ig_mask_l0(4, 1), M2 = ig_mask_lk(4, 1); };
-template <> struct Fam<2> { static constexpr int U1 = 14, U2 = 14;
+template <> struct Fam<2> { static constexpr int U1 = 14, U2 = 14, WAVES = 8;
                             static constexpr uint64_t M1 = ig_mask_l0(8, 2), M2 = ig_mask_lk(8, 2); };
-template <> struct Fam<3> { static constexpr int U1 = 30, U2 = 30;
+template <> struct Fam<3> { static constexpr int U1 = 30, U2 = 30, WAVES = 7;
                             static constexpr uint64_t M1 = ig_mask_l0(16, 3), M2 = ig_mask_lk(16, 3); };
-template <> struct Fam<4> { static constexpr int U1 = 8, U2 = 8;
+template <> struct Fam<4> { static constexpr int U1 = 8, U2 = 8, WAVES = 8;
                             static constexpr uint64_t M1 = run_mask(8), M2 = run_mask(8); };
-template <> struct Fam<5> { static constexpr int U1 = 16, U2 = 16;
+template <> struct Fam<5> { static constexpr int U1 = 16, U2 = 16, WAVES = 8;
                             static constexpr uint64_t M1 = run_mask(16), M2 = run_mask(16); };
-template <> struct Fam<6> { static constexpr int U1 = 32, U2 = 32;
+template <> struct Fam<6> { static constexpr int U1 = 32, U2 = 32, WAVES = 8;
                             static constexpr uint64_t M1 = run_mask(32), M2 = run_mask(32); };
-template <> struct Fam<7> { static constexpr int U1 = 1, U2 = 1; static constexpr uint64_t M1 = 1, M2 = 1; };
+template <> struct Fam<7> { static constexpr int U1 = 1, U2 = 1, WAVES = 8;
+                            static constexpr uint64_t M1 = 1, M2 = 1; };
 
 // All widths of the group fit: straight-line evaluation of a compiled-in width pattern.
 // X enters holding the carried prefixes and leaves holding the sum over UMAX units.
@@ -172,7 +176,7 @@ __device__ __forceinline__ void bank_generic(const float *y, const float *rt, in
 }
 
 template <bool FIRST, int FAM>
-__global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
+__global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(const StepArgs A) {
     extern __shared__ float lds[];
     __shared__ uint32_t st_cnt[kStepMaxLevels];
 
@@ -229,27 +233,30 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
     }
     lds_barrier();
 
-    // ---- 2+3. cascade fused with the width sets: while level j's boxcars are evaluated, each
-    // group also forms level j+1's units from its window (into the buffer level j-1 used), so a
-    // level costs one pass over LDS and one barrier, and only two level buffers are live.
+    // ---- 2+3. cascade fused with the width sets.  Level j is evaluated in batches of
+    // kStepThreads groups; each group also forms its two units of level j+1 (and, for BoxDIT,
+    // its two carried prefixes) in registers.  After a barrier that ends the batch's reads they
+    // are written in place: unit n of level j+1 goes to index n of the same buffer, below every
+    // unit of level j a later batch still reads (and likewise for the carries).  The units of
+    // level j+1 past the tile's slots (its halo) are formed after the last batch.
     const int jtop = A.has_out ? A.J : A.J - 1;
+    float *ybuf = lds + A.lv[0].lds_y;
+    float *cbuf = lds + A.lv[0].lds_c;
     for (int j = 0; j < A.J; ++j) {
         const bool form_next = j + 1 <= jtop;
-        float *yn = form_next ? lds + A.lv[j + 1].lds_y : nullptr;
         const int cs1 = form_next ? A.lv[j + 1].cshift : 0;
         const int n_next = form_next ? A.lv[j + 1].n_units : 0;
         const StepLevel &L = A.lv[j];
         const int Sj = T >> j;
         const int ms0 = tile * Sj;                         // absolute slot of tile slot 0
         const int ngroups = Sj / kGroup;
-        const float *yj = lds + L.lds_y;
-        const float *cj = lds + L.lds_c;
+        const float *yj = ybuf;
+        const float *cj = cbuf;
         const bool has_carry = A.carry && (j > 0 || A.cin != nullptr);
         const bool to_lds = A.carry && (j + 1 < A.J);
         const bool to_glb = A.carry && (j + 1 == A.J) && A.has_out;
-        float *cn = to_lds ? lds + A.lv[j + 1].lds_c
-                           : (to_glb ? A.cout + (int64_t)d * A.ld_out + (int64_t)tile * (T >> A.J)
-                                     : nullptr);
+        float *cg = to_glb ? A.cout + (int64_t)d * A.ld_out + (int64_t)tile * (T >> A.J) : nullptr;
+        const bool sync_batches = form_next || to_lds;   // a batch writes into the live buffers
         const int k = L.k;
         const int umax = L.umax;
         const int base = L.base;
@@ -271,15 +278,17 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
                 best[q] = SPD_NEG_INF;
                 bu[q] = 0;
             }
+            // y_{j+1}[n] = y_j[2n + cshift] + y_j[2n + cshift + 1] for 2n + cshift = m0, m0 + 2
+            const int n0 = (m0 - cs1) >> 1;
+            float nu0 = 0.0f, nu1 = 0.0f;
             if (form_next && g < ngroups) {
-                // y_{j+1}[n] = y_j[2n + cshift] + y_j[2n + cshift + 1] for 2n + cshift = m0, m0 + 2
                 const float4 w0 = *reinterpret_cast<const float4 *>(yj + m0);
-                const int n0 = (m0 - cs1) >> 1;
-                if (n0 >= 0 && n0 < n_next) yn[n0] = w0.x + w0.y;
-                if (n0 + 1 >= 0 && n0 + 1 < n_next) yn[n0 + 1] = w0.z + w0.w;
+                nu0 = w0.x + w0.y;
+                nu1 = w0.z + w0.w;
             }
+            float Xc[kGroup];
             if (act) {
-                float X[kGroup], Xc[kGroup];
+                float X[kGroup];
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) X[q] = has_carry ? cj[m0 + q] : 0.0f;
                 const bool fast = ((int64_t)(ma + kGroup - 1) << k) <= fast_lim;
@@ -297,10 +306,10 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
                     for (int q = 0; q < kGroup; ++q) room[q] = (int64_t)A.n_in - ((int64_t)(ma + q) << k);
                     bank_generic(yj + m0, rt, umax, L.evalmask, L.ufull, k, base, room, X, Xc, best, bu);
                 }
-                if (cn) {
-                    // this level's longest boxcar is the next level's carried prefix
-                    cn[(m0 >> 1) + 0] = Xc[0];
-                    cn[(m0 >> 1) + 1] = Xc[2];
+                if (cg) {
+                    // the last level's longest boxcar is the next step's carried prefix
+                    cg[(m0 >> 1) + 0] = Xc[0];
+                    cg[(m0 >> 1) + 1] = Xc[2];
                 }
                 int bw[kGroup];
 #pragma unroll
@@ -352,20 +361,33 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs A) {
                     }
                 }
             }
-        }
-        if (form_next) {
-            // units of level j+1 beyond the tile's slots (its halo)
-            for (int n = max(0, (Sj - cs1) >> 1) + tid; n < n_next; n += kStepThreads) {
-                const float2 p = *reinterpret_cast<const float2 *>(yj + 2 * n + cs1);
-                yn[n] = p.x + p.y;
+            if (sync_batches) {
+                lds_barrier();                   // the batch's reads of level j are done
+                if (form_next && g < ngroups) {
+                    float *yn = ybuf;
+                    if (n0 >= 0 && n0 < n_next) yn[n0] = nu0;
+                    if (n0 + 1 >= 0 && n0 + 1 < n_next) yn[n0 + 1] = nu1;
+                }
+                if (to_lds && act) {
+                    // this level's longest boxcar is the next level's carried prefix
+                    cbuf[(m0 >> 1) + 0] = Xc[0];
+                    cbuf[(m0 >> 1) + 1] = Xc[2];
+                }
             }
         }
-        lds_barrier();                       // level j+1 is complete; level j's buffer is reused
+        if (form_next) {
+            // halo units of level j+1: read at index >= S_j, written below it
+            for (int n = max(0, (Sj - cs1) >> 1) + tid; n < n_next; n += kStepThreads) {
+                const float2 p = *reinterpret_cast<const float2 *>(yj + 2 * n + cs1);
+                ybuf[n] = p.x + p.y;
+            }
+        }
+        lds_barrier();                       // level j+1 is complete
     }
 
     // ---- 4. hand on the last formed level
     if (A.has_out) {
-        const float *yJ = lds + A.lv[A.J].lds_y;
+        const float *yJ = lds + A.lv[0].lds_y;
         float *o = A.out + (int64_t)d * A.ld_out + (int64_t)tile * (T >> A.J);
         for (int n = tid; n < (T >> A.J); n += kStepThreads) o[n] = yJ[n];
     }

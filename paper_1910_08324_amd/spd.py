@@ -20,6 +20,8 @@ SPD_OK, SPD_EINVAL, SPD_EALIGN, SPD_EWORKSPACE, SPD_EHIP = 0, -1, -2, -3, -4
 EXHAUSTIVE, BOXDIT, IGRID = 0, 1, 2
 WRITE_PLANES, WRITE_CANDIDATES = 1, 2
 MAX_LEVELS = 24
+MAX_LAUNCHES = 26
+ABI_VERSION = 2
 
 
 class Params(ctypes.Structure):
@@ -53,6 +55,11 @@ class PlanInfo(ctypes.Structure):
         ("workspace_bytes", ctypes.c_int64),
         ("segment", ctypes.c_int32),
         ("n_segments", ctypes.c_int32),
+        ("n_launches", ctypes.c_int32),
+        ("launch_first_level", ctypes.c_int32 * MAX_LAUNCHES),
+        ("launch_levels", ctypes.c_int32 * MAX_LAUNCHES),
+        ("launch_in_units", ctypes.c_int64 * MAX_LAUNCHES),
+        ("launch_out_units", ctypes.c_int64 * MAX_LAUNCHES),
     ]
 
 
@@ -83,6 +90,10 @@ def load():
         lib.spd_filter.argtypes = [ctypes.POINTER(Params), P, i64, i32, i32, i32, P, P, P, P, P,
                                    i64, P]
         lib.spd_filter.restype = ctypes.c_int
+        lib.spd_filter_timed.argtypes = [ctypes.POINTER(Params), P, i64, i32, i32, i32, P, P, P,
+                                         P, P, i64, P, ctypes.POINTER(ctypes.c_float), i32,
+                                         ctypes.POINTER(i32)]
+        lib.spd_filter_timed.restype = ctypes.c_int
         lib.spd_peaks.argtypes = [ctypes.POINTER(Params), i32, i32, i32, i64, P, P, P, i64, P, P,
                                   i64, P]
         lib.spd_peaks.restype = ctypes.c_int
@@ -90,6 +101,9 @@ def load():
         lib.spd_error_string.restype = ctypes.c_char_p
         lib.spd_abi_version.argtypes = []
         lib.spd_abi_version.restype = ctypes.c_int
+        if lib.spd_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {lib.spd_abi_version()}, this binding "
+                               f"expects {ABI_VERSION}: rebuild it")
         _lib = lib
     return _lib
 
@@ -323,6 +337,17 @@ class Runner:
         _check(self._lib.spd_filter(self._p, self._x, self._ld, self.n_dm, self.n_in, self.n_out,
                                     self._mu, self._sg, self._Y, self._W, self._ws,
                                     self.workspace.numel(), self._s), "spd_filter")
+
+    def filter_timed(self) -> List[float]:
+        """Run the filter once with HIP events around each kernel launch on the runner's stream;
+        blocks until done and returns the launches' durations (ms), in plan order."""
+        ms = (ctypes.c_float * MAX_LAUNCHES)()
+        n = ctypes.c_int32()
+        _check(self._lib.spd_filter_timed(self._p, self._x, self._ld, self.n_dm, self.n_in,
+                                          self.n_out, self._mu, self._sg, self._Y, self._W,
+                                          self._ws, self.workspace.numel(), self._s, ms,
+                                          MAX_LAUNCHES, ctypes.byref(n)), "spd_filter_timed")
+        return [float(ms[i]) for i in range(n.value)]
 
     def peaks(self):
         _check(self._lib.spd_peaks(self._p, self.n_dm, self.n_in, self.n_out, self.t0, self._Y,

@@ -26,7 +26,7 @@ def test_exports_every_declared_symbol(lib):
                           "spd_abi_version"}
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.spd_abi_version() == 1
+    assert lib.spd_abi_version() == spd.ABI_VERSION == 2
 
 
 CASES = [("exh", 1), ("exh", 256), ("exh", 8192), ("dit", 8192)] + \
@@ -61,6 +61,38 @@ def test_level_widths_more_variants(lib):
     assert spd.level_widths(cfg) == [w for _, w in ow.boxdit_levels([16, 8, 4, 32], 3000)]
     cfg = spd.Config("exh", 50, widths=[1, 3, 9, 50])
     assert spd.level_widths(cfg) == [[1, 3, 9, 50]]
+
+
+@pytest.mark.parametrize("method,l_end", [("ig1", 8192), ("ig3", 8192), ("bd8", 8192),
+                                          ("bd32", 8192), ("dit", 65535), ("ig2", 5),
+                                          ("exh", 8192)])
+def test_launch_list_covers_every_level_once(lib, method, l_end):
+    n_dm, n = 7, 262144
+    info = spd.plan(spd.Config(method, l_end), n_dm, n)
+    nl = info.n_launches
+    assert 1 <= nl <= spd.MAX_LAUNCHES
+    first = [info.launch_first_level[i] for i in range(nl)]
+    nlev = [info.launch_levels[i] for i in range(nl)]
+    work = [(f, c) for f, c in zip(first, nlev) if f >= 0]
+    # the computing launches tile the levels in order
+    assert [f for f, _ in work] == [sum(c for _, c in work[:i]) for i in range(len(work))]
+    assert sum(c for _, c in work) == info.n_levels
+    setup = [i for i in range(nl) if first[i] < 0]
+    assert all(nlev[i] == 0 for i in setup)
+    w0 = first.index(0)
+    assert info.launch_in_units[w0] == n
+    assert info.launch_out_units[nl - 1] == 0
+    if method == "exh":
+        assert len(work) == 1 and len(setup) == 1
+        return
+    assert not setup
+    series = 2 if method.startswith("bd") else 1
+    for i in range(1, nl):
+        # each cascade launch reads what the previous one handed on
+        assert info.launch_in_units[i] == info.launch_out_units[i - 1] > 0
+        k = info.level_shift[first[i]]
+        assert info.launch_in_units[i] >= series * (n >> k) // 2
+    assert all(c <= 6 for c in nlev)
 
 
 def test_plan_geometry(lib):
