@@ -195,15 +195,24 @@ def main():
         for _ in range(4):
             run.search()
         torch.cuda.synchronize()
+        # plain streaming kernels of known size, in this order, for scaling the counters
         copy_bytes = x.numel() * 4
         y = torch.empty_like(x)
-        torch.mul(x, 1.0, out=y)            # plain streaming kernel: reads and writes copy_bytes
+        torch.mul(x, 1.0, out=y)                            # contiguous: copy_bytes each way
         torch.cuda.synchronize()
+        torch.mul(x[:, 64:], 1.0, out=y[:, 64:])            # row-strided view
+        torch.cuda.synchronize()
+        y.copy_(x)                                          # device-to-device copy
+        torch.cuda.synchronize()
+        strided_bytes = x[:, 64:].numel() * 4
         launches = [{"kernel": launch_kernel_name(args.method, info, i),
                      "algorithmic_bytes": launch_bytes(info, i, w.n_dm)}
                     for i in range(info.n_launches)]
         print(json.dumps({"probe": "ok", "method": args.method, "search_launches": 4,
                           "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes,
+                          "copies": [{"op": "mul", "bytes": copy_bytes},
+                                     {"op": "mul_strided", "bytes": strided_bytes},
+                                     {"op": "copy", "bytes": copy_bytes}],
                           "launches": launches,
                           "algorithmic_bytes_filter": algorithmic_bytes(info, w.n_dm, w.n),
                           "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
