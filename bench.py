@@ -163,6 +163,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample time")
     ap.add_argument("--segment", type=int, default=0, help="tile length override (0: library's)")
     ap.add_argument("--profile-probe", action="store_true")
+    ap.add_argument("--proposal-tiles", type=int, default=65536,
+                    help="tiles of 64 x 4096 to train the learned proposal on (0: skip)")
+    ap.add_argument("--proposal-eval", type=int, default=8192, help="held-out evaluation tiles")
+    ap.add_argument("--proposal-batch", type=int, default=256)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -364,6 +368,11 @@ def main():
                          f"(FP64 oracle, {spent:.1f} s)"}
         log(f"[bench] cpu oracle: {cpu['value']:.3e} DM*samples/s on {cpu['cores']} threads")
 
+    prop = None
+    if args.proposal_tiles > 0:
+        torch.cuda.empty_cache()
+        prop = proposal_section(args, dev)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -394,7 +403,103 @@ def main():
         out["speedup_vs_exhaustive"] = rtf / methods["exh"]["rtf"]
     if "mean_loss" in methods.get(args.method, {}):
         out["mean_loss_vs_exhaustive"] = methods[args.method]["mean_loss"]
+    if prop is not None:
+        out["proposal"] = prop
     print(json.dumps(out), flush=True)
+
+
+def proposal_section(args, dev) -> dict:
+    """Train the learned tile proposal on GPU-generated tiles labelled by the library's own
+    exhaustive and IG(1) searches (L_end 256, the small exhaustive workload's widths), then
+    evaluate it on held-out tiles against the exhaustive search."""
+    import numpy as np
+    import torch
+    from paper_1910_08324_amd import proposal as P
+
+    B = args.proposal_batch
+    x = torch.empty((B * P.TILE_ROWS, P.TILE_LEN), dtype=torch.float32, device=dev)
+    lab = P.Labeller(x)
+    net = P.Network(P.init_params(0), device=dev, max_tiles=B)
+    steps = max(1, args.proposal_tiles // B)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    parts = np.zeros(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    first_loss = None
+    for i in range(steps):
+        ev[0].record()
+        P.generate_tiles(1, i * B, B, out=x)
+        ev[1].record()
+        lab.r_lossy.filter()
+        P.tile_max(lab.r_lossy.result.snr, lab.r_lossy.info, x.shape[0], P.TILE_ROWS, lab.lossy_max)
+        lab.r_exh.filter()
+        P.tile_max(lab.r_exh.result.snr, lab.r_exh.info, x.shape[0], P.TILE_ROWS, lab.exh_max)
+        P.labels(lab.exh_max, lab.lossy_max, lab.threshold, lab.margin, lab.labels)
+        ev[2].record()
+        P.features(x, lab.mean, lab.sigma, lab.feat)
+        ev[3].record()
+        net.backward(lab.feat, lab.labels, B)
+        ev[4].record()
+        net.adam(2e-3)
+        ev[5].record()
+        if i == 0:
+            first_loss = float(net.loss.item())
+        if i % 64 == 0 or i == steps - 1:
+            torch.cuda.synchronize()
+            for k in range(5):
+                parts[k] += ev[k].elapsed_time(ev[k + 1])
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    last_loss = float(net.loss.item())
+    sampled = len(range(0, steps, 64)) + (0 if (steps - 1) % 64 == 0 else 1)
+    per_batch = parts / sampled
+    log(f"[bench] proposal: trained on {steps * B} tiles in {train_s:.1f} s "
+        f"({steps * B / train_s:.0f} tiles/s), loss {first_loss:.4f} -> {last_loss:.4f}")
+    # inference throughput: features + forward on one batch
+    lg = torch.empty(B, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        P.features(x, lab.mean, lab.sigma, lab.feat)
+        net.forward(lab.feat, B, lg)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        P.features(x, lab.mean, lab.sigma, lab.feat)
+        net.forward(lab.feat, B, lg)
+    e1.record()
+    torch.cuda.synchronize()
+    inf_ms = e0.elapsed_time(e1) / 10
+    res = P.evaluate(net, args.proposal_eval, batch=B, seed=1, labeller=lab)
+    # modelled cost per tile of each path, from the measured per-batch stage times
+    t_lossy = t_exh = 0.0
+    e0.record()
+    lab.r_lossy.filter()
+    e1.record()
+    torch.cuda.synchronize()
+    t_lossy = e0.elapsed_time(e1)
+    e0.record()
+    lab.r_exh.filter()
+    e1.record()
+    torch.cuda.synchronize()
+    t_exh = e0.elapsed_time(e1)
+    cost_prop = t_lossy + inf_ms + res["flag_rate"] * t_exh
+    log(f"[bench] proposal: recall {res['recall']:.3f}, flag rate {res['flag_rate']:.3f}, mean loss "
+        f"lossy {res['mean_loss_lossy'] * 100:.2f}% -> with proposal "
+        f"{res['mean_loss_with_proposal'] * 100:.2f}%")
+    return {"train_tiles": steps * B, "batch": B, "train_seconds": round(train_s, 2),
+            "train_tiles_per_s": round(steps * B / train_s, 1),
+            "loss_first": round(first_loss, 5), "loss_last": round(last_loss, 5),
+            "ms_per_batch": {"generate": round(per_batch[0], 3), "label": round(per_batch[1], 3),
+                             "features": round(per_batch[2], 3),
+                             "forward_backward": round(per_batch[3], 3),
+                             "adam": round(per_batch[4], 3)},
+            "inference_ms_per_batch": round(inf_ms, 4),
+            "inference_tiles_per_s": round(B / (inf_ms * 1e-3), 1),
+            "eval": res,
+            "ms_per_batch_lossy": round(t_lossy, 4), "ms_per_batch_exhaustive": round(t_exh, 4),
+            "ms_per_batch_lossy_plus_proposal": round(cost_prop, 4),
+            "workload": "tiles of 64 DM x 4096 samples, N(0,1) noise + 0-2 boxcar pulses "
+                        "(width 1-64, SNR 6-30), labels: exhaustive 1..256 vs IG(1) L_end 256, "
+                        "threshold 6, margin 1%"}
 
 
 if __name__ == "__main__":

@@ -20,10 +20,15 @@ def lib():
 
 
 def test_exports_every_declared_symbol(lib):
-    hdr = open(os.path.join(ROOT, "include", "spd.h")).read()
-    names = re.findall(r"^\w[\w\s\*]*?\b(spd_\w+)\s*\(", hdr, flags=re.M)
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            hdr = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^\w[\w\s\*]*?\b(spd_\w+)\s*\(", hdr, flags=re.M)
     assert set(names) >= {"spd_plan", "spd_level_widths", "spd_search", "spd_error_string",
-                          "spd_abi_version"}
+                          "spd_abi_version", "spd_filter_timed", "spd_tiles_generate",
+                          "spd_prop_features", "spd_prop_forward", "spd_prop_backward",
+                          "spd_prop_adam", "spd_tile_max", "spd_prop_labels"}
     for n in names:
         assert hasattr(lib, n), n
     assert lib.spd_abi_version() == spd.ABI_VERSION == 2
@@ -184,3 +189,33 @@ def test_plan_accepts_wide_range(lib, method):
                     assert seg != 0 and e.status == spd.SPD_EINVAL, (l_end, n, seg)
                     continue
                 assert info.workspace_bytes > 0
+
+
+def test_proposal_host_checks(lib):
+    """Argument checks and workspace sizing of the proposal entry points (no device work)."""
+    from paper_1910_08324_amd import proposal as P
+    L = P.lib()
+    assert L.spd_tiles_generate(1, 0, 0, None, None) == spd.SPD_EINVAL
+    assert L.spd_tiles_generate(1, -1, 4, ctypes.c_void_p(256), None) == spd.SPD_EINVAL
+    assert L.spd_prop_features(None, 4096, 64, None, None, None, None) == spd.SPD_EINVAL
+    b1, b2 = P.workspace_bytes(1), P.workspace_bytes(8)
+    assert b1 > 0 and b2 > b1 and b1 % 256 == 0
+    assert L.spd_prop_forward(ctypes.c_void_p(256), ctypes.c_void_p(256), 1, ctypes.c_void_p(256),
+                              ctypes.c_void_p(256), b1 - 1, None) == spd.SPD_EWORKSPACE
+    assert L.spd_prop_adam(None, None, None, None, 1, 0.1, None) == spd.SPD_EINVAL
+    assert L.spd_prop_labels(None, None, 4, 6.0, 0.01, None, None) == spd.SPD_EINVAL
+    info = spd.plan(spd.Config("ig1", 256), 128, 4096)
+    assert L.spd_tile_max(ctypes.c_void_p(256), ctypes.byref(info), 100, 64, ctypes.c_void_p(256),
+                          None) == spd.SPD_EINVAL
+
+
+def test_proposal_pack_roundtrip(lib):
+    import numpy as np
+    from paper_1910_08324_amd import proposal as P
+    v = P.init_params(3)
+    assert v.shape == (P.NPARAMS,) and v.dtype == np.float32
+    u = P.unpack(v)
+    assert np.array_equal(P.pack(u), v)
+    assert u["W1"].shape == (32, 5, 5) and u["W2"].shape == (32, 5, 32)
+    W1 = v[:1280].reshape(32, 5, 8)
+    assert np.all(W1[:, :, 5:] == 0)
