@@ -102,7 +102,8 @@ def test_forward_matches_oracle(P):
     F = bf16_host(feat)[:, 2:258, :5]
     ref = op.forward(F, net, bf16=True)["logits"]
     say(f"  logits gpu {lg} oracle {ref}")
-    assert np.allclose(lg, ref, rtol=2e-3, atol=2e-3)
+    # FP32 accumulation on the GPU vs FP64 here, same bfloat16 roundings: ~1e-6 observed
+    assert np.allclose(lg, ref, rtol=1e-4, atol=1e-4)
 
 
 @pytest.mark.parametrize("seed", [21, 22])
@@ -126,7 +127,7 @@ def test_backward_matches_oracle(P, seed):
         b = np.asarray(getattr(ref, n), np.float64)
         err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
         say(f"  {n}: relative error {err:.2e}")
-        assert err < 2e-2, n
+        assert err < 1e-3, n       # ~1e-6 .. 1e-5 observed
     pad = g[P.OFF["W1"]:P.OFF["W1"] + 1280].reshape(32, 5, 8)[:, :, 5:]
     assert np.all(pad == 0) and np.all(g[P.OFF["bh"] + 1:] == 0)
 
@@ -180,6 +181,7 @@ def test_training_gains_over_lossy_alone(P):
     ev = P.evaluate(N, 128 * 16, batch=128, seed=3)
     say(f"  evaluation {ev}")
     assert hist[-1][1] < hist[0][1]
-    assert ev["recall"] > 0.6
-    assert ev["flag_rate"] < 0.6
-    assert ev["mean_loss_with_proposal"] < 0.6 * ev["mean_loss_lossy"]
+    pos_rate = ev["positives"] / ev["tiles"]
+    assert ev["recall"] > 0.7 and ev["precision"] > 0.8
+    assert ev["flag_rate"] < pos_rate + 0.15
+    assert ev["mean_loss_with_proposal"] < 0.5 * ev["mean_loss_lossy"]
