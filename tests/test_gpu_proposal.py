@@ -172,8 +172,8 @@ def test_tile_max_and_labels_match_oracle(P):
 
 def test_training_gains_over_lossy_alone(P):
     """Train on GPU-generated tiles with the library's own kernels; on held-out tiles the
-    proposal must recover most of the signal power the lossy search misses, flagging a
-    minority of the tiles."""
+    proposal must recover most of the signal power the lossy search misses while flagging few
+    tiles beyond the positive ones."""
     say("[proposal] training")
     N = P.Network(P.init_params(0), max_tiles=128)
     hist = P.train(N, 128 * 48, batch=128, seed=3, lr=3e-3, log_every=12)
