@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SPD_ABI_VERSION 2
+#define SPD_ABI_VERSION 3
 
 /* Status codes. */
 #define SPD_OK          0
@@ -83,6 +83,9 @@ extern "C" {
  *                   depend on it.  BoxDIT / IGRID: a multiple of 256 in 256..32768 that leaves
  *                   every launch of the level cascade room for its halo and its on-chip buffers
  *                   (spd_plan returns SPD_EINVAL otherwise); exhaustive: 256 only.
+ *   step_levels     BoxDIT / IGRID: separation levels computed on chip per kernel launch, 1..6,
+ *                   or 0 for the library's choice (6, fewer if a tile's buffers would not fit).
+ *                   Results do not depend on it.  Exhaustive: must be 0.
  */
 typedef struct {
     int32_t method;
@@ -96,6 +99,7 @@ typedef struct {
     float threshold;
     uint32_t flags;
     int32_t segment;
+    int32_t step_levels;
 } spd_params;
 
 /* One candidate (24 bytes).  start = t0 + m 2^k is the first sample of the boxcar; the pulse

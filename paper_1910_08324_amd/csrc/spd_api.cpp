@@ -11,6 +11,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include "spd.h"
+#include "spd_batch.h"
 #include "spd_internal.h"
 
 namespace {
@@ -308,6 +309,7 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
     };
     if (!lossy) {
         if (p->segment != 0 && p->segment != spd::kExhSlots) return SPD_EINVAL;
+        if (p->step_levels != 0) return SPD_EINVAL;
         L->exh_nseg = (int)ceil_div(n_out, spd::kExhSlots);
         I.segment = spd::kExhSlots;
         I.n_segments = L->exh_nseg;
@@ -320,11 +322,13 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
         const bool fixed_T = p->segment != 0;
         int T = fixed_T ? p->segment : 4096;
         if (T < 256 || T > 32768 || T % 256) return SPD_EINVAL;
+        if (p->step_levels < 0 || p->step_levels > spd::kStepMaxLevels) return SPD_EINVAL;
+        const int jmax = p->step_levels ? p->step_levels : spd::kStepMaxLevels;
         int k0 = 0;
         int64_t in_len = n_in;
         while (k0 <= K) {
             StepPlan st;
-            int J = std::min(spd::kStepMaxLevels, K + 1 - k0);
+            int J = std::min(jmax, K + 1 - k0);
             int Tj = T;
             int lds = -1;
             for (;;) {
@@ -334,7 +338,7 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
                     --J;
                 } else if (!fixed_T && Tj > 256) {
                     Tj >>= 1;
-                    J = std::min(spd::kStepMaxLevels, K + 1 - k0);
+                    J = std::min(jmax, K + 1 - k0);
                 } else {
                     return SPD_EINVAL;
                 }
@@ -499,6 +503,21 @@ int prepare(const spd_params *params, int32_t n_dm, int32_t n_in, int32_t n_out,
     return SPD_OK;
 }
 
+// The fields of a cascade launch's arguments that do not depend on the beam.
+void fill_step_shared(const spd_params *params, const Search &s, const StepPlan &st, size_t si,
+                      spd::StepArgs *a) {
+    std::memset(a, 0, sizeof(*a));
+    a->T = st.T;
+    a->J = st.J;
+    a->has_out = st.has_out;
+    a->normalise = si == 0;
+    a->carry = s.method == SPD_BOXDIT;
+    a->want_cand = (params->flags & SPD_WRITE_CANDIDATES) != 0;
+    a->threshold = params->threshold;
+    for (int j = 0; j <= st.J && j <= spd::kStepMaxLevels; ++j) a->lv[j] = st.lv[j];
+    std::memcpy(a->rtab, st.rtab, sizeof(a->rtab));
+}
+
 // HIP events recorded before the first launch and after each launch (spd_filter_timed).
 struct LaunchMarks {
     hipStream_t stream = nullptr;
@@ -534,7 +553,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
         for (size_t si = 0; si < L.steps.size(); ++si) {
             const StepPlan &st = L.steps[si];
             spd::StepArgs a;
-            std::memset(&a, 0, sizeof(a));
+            fill_step_shared(params, s, st, si, &a);
             a.in = in;
             a.cin = cin;
             a.out = st.has_out ? reinterpret_cast<float *>(P.ws + st.off_out) : nullptr;
@@ -552,17 +571,8 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
             a.n_dm = n_dm;
             a.n_in = n_in;
             a.in_len = (int32_t)st.in_len;
-            a.T = st.T;
             a.n_tiles = st.tiles;
-            a.J = st.J;
-            a.has_out = st.has_out;
-            a.normalise = si == 0;
-            a.carry = s.method == SPD_BOXDIT;
             a.vec_ok = si == 0 ? vec_ok : 1;
-            a.want_cand = want_cand;
-            a.threshold = params->threshold;
-            for (int j = 0; j <= st.J && j <= spd::kStepMaxLevels; ++j) a.lv[j] = st.lv[j];
-            std::memcpy(a.rtab, st.rtab, sizeof(a.rtab));
             const int err = spd::launch_step(a, s.fam, st.lds_bytes, hip_stream);
             if (err) return hip_fail(err);
             if (const int e2 = mark()) return hip_fail(e2);
@@ -658,6 +668,103 @@ int run_peaks(const spd_params *params, const Prepared &P, int32_t n_dm, int64_t
     return SPD_OK;
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Batches of beams (spd_batch.h)
+// ---------------------------------------------------------------------------------------
+struct BatchPlan {
+    Search s;
+    std::vector<Layout> L;
+    std::vector<int64_t> ws_off;
+    int64_t ws_total = 0;
+    int64_t table_bytes = 0;
+    int64_t base_off = 0;       // offset of the item_base arrays in the table
+    int n_steps = 0;
+};
+
+int batch_plan(const spd_params *params, int32_t n_beams, const spd_beam *beams, BatchPlan *B) {
+    if (!params || !beams || n_beams < 1 || n_beams > (1 << 16)) return SPD_EINVAL;
+    if (params->method == SPD_EXHAUSTIVE) return SPD_EINVAL;
+    int st = build_search(params, &B->s);
+    if (st != SPD_OK) return st;
+    B->L.resize(n_beams);
+    B->ws_off.resize(n_beams);
+    int64_t off = 0;
+    for (int b = 0; b < n_beams; ++b) {
+        st = make_layout(params, B->s, beams[b].n_dm, beams[b].n_in, beams[b].n_out, &B->L[b]);
+        if (st != SPD_OK) return st;
+        const std::vector<StepPlan> &S = B->L[b].steps;
+        const std::vector<StepPlan> &S0 = B->L[0].steps;
+        if (S.size() != S0.size()) return SPD_EINVAL;
+        for (size_t i = 0; i < S.size(); ++i)
+            if (S[i].k0 != S0[i].k0 || S[i].J != S0[i].J || S[i].T != S0[i].T ||
+                S[i].lds_bytes != S0[i].lds_bytes)
+                return SPD_EINVAL;
+        B->ws_off[b] = off;
+        off += round_up(B->L[b].info.workspace_bytes, 256);
+    }
+    B->n_steps = (int)B->L[0].steps.size();
+    B->ws_total = off;
+    B->base_off = round_up((int64_t)B->n_steps * n_beams * (int64_t)sizeof(spd::BeamView), 256);
+    B->table_bytes = B->base_off + (int64_t)B->n_steps * (n_beams + 1) * 8;
+    return SPD_OK;
+}
+
+// the beam's view of cascade step si: its buffers in the caller's memory and its workspace
+spd::BeamView beam_view(const spd_params *params, const BatchPlan &B, const spd_beam &bm, int b,
+                        int si, char *ws_base) {
+    const Layout &L = B.L[b];
+    const StepPlan &st = L.steps[si];
+    char *ws = ws_base + B.ws_off[b];
+    const bool planes = params->flags & SPD_WRITE_PLANES;
+    spd::BeamView v;
+    std::memset(&v, 0, sizeof(v));
+    if (si == 0) {
+        v.in = bm.x;
+        v.ld_in = bm.ld;
+        v.vec_ok = (((uintptr_t)bm.x & 15) == 0) && (bm.ld % 4 == 0);
+    } else {
+        const StepPlan &pv = L.steps[si - 1];
+        v.in = reinterpret_cast<const float *>(ws + pv.off_out);
+        v.cin = pv.off_cout >= 0 ? reinterpret_cast<const float *>(ws + pv.off_cout) : nullptr;
+        v.ld_in = pv.ld_out;
+        v.vec_ok = 1;
+    }
+    v.ld_cin = v.ld_in;
+    v.out = st.has_out ? reinterpret_cast<float *>(ws + st.off_out) : nullptr;
+    v.cout = (st.has_out && st.off_cout >= 0) ? reinterpret_cast<float *>(ws + st.off_cout) : nullptr;
+    v.ld_out = st.ld_out;
+    v.mean = bm.mean;
+    v.sigma = bm.sigma;
+    v.Y = planes ? bm.snr : reinterpret_cast<float *>(ws + L.off_Y);
+    v.W = planes ? bm.width : reinterpret_cast<uint16_t *>(ws + L.off_W);
+    v.slab_cnt = reinterpret_cast<uint32_t *>(ws + L.off_cnt);
+    v.slab_ent = reinterpret_cast<uint32_t *>(ws + L.off_ent);
+    v.n_dm = bm.n_dm;
+    v.n_in = bm.n_in;
+    v.in_len = (int32_t)st.in_len;
+    v.n_tiles = st.tiles;
+    for (int j = 0; j < st.J; ++j) {
+        v.plane_off[j] = st.lv[j].plane_off;
+        v.pitch[j] = st.lv[j].pitch;
+        v.slab_base[j] = st.lv[j].slab_base;
+        v.slots[j] = st.lv[j].slots;
+    }
+    return v;
+}
+
+int check_beam(const spd_params *params, const BatchPlan &B, const spd_beam &bm, int b) {
+    const bool planes = params->flags & SPD_WRITE_PLANES;
+    const bool cands = params->flags & SPD_WRITE_CANDIDATES;
+    if (!bm.x || !bm.mean || !bm.sigma || bm.ld < bm.n_in) return SPD_EINVAL;
+    if (planes && (!bm.snr || !bm.width)) return SPD_EINVAL;
+    if (planes && ((((uintptr_t)bm.snr) & 15) || (((uintptr_t)bm.width) & 7))) return SPD_EALIGN;
+    if (cands && (bm.cand_cap < 0 || (bm.cand_cap > 0 && !bm.cand) || !bm.cand_count))
+        return SPD_EINVAL;
+    if (bm.t0 < 0 || (bm.t0 & (((int64_t)1 << B.L[b].info.top_level) - 1))) return SPD_EALIGN;
+    return SPD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -723,6 +830,85 @@ int spd_search(const spd_params *params, const float *x, int64_t ld, int32_t n_d
     st = run_filter(params, P, x, ld, n_dm, n_in, n_out, mean, sigma, hip_stream);
     if (st != SPD_OK || !want_cand) return st;
     return run_peaks(params, P, n_dm, t0, cand, cand_cap, cand_count, hip_stream);
+}
+
+int spd_batch_plan(const spd_params *params, int32_t n_beams, const spd_beam *beams,
+                   int64_t *workspace_bytes, int64_t *table_bytes) {
+    if (!workspace_bytes || !table_bytes) return SPD_EINVAL;
+    BatchPlan B;
+    const int st = batch_plan(params, n_beams, beams, &B);
+    if (st != SPD_OK) return st;
+    *workspace_bytes = std::max<int64_t>(B.ws_total, 256);
+    *table_bytes = B.table_bytes;
+    return SPD_OK;
+}
+
+int spd_batch_table(const spd_params *params, int32_t n_beams, const spd_beam *beams,
+                    void *workspace, void *table, int64_t table_bytes) {
+    BatchPlan B;
+    const int st = batch_plan(params, n_beams, beams, &B);
+    if (st != SPD_OK) return st;
+    if (!workspace || !table || table_bytes < B.table_bytes) return SPD_EINVAL;
+    if ((uintptr_t)workspace & 255) return SPD_EALIGN;
+    char *t = static_cast<char *>(table);
+    spd::BeamView *views = reinterpret_cast<spd::BeamView *>(t);
+    int64_t *base = reinterpret_cast<int64_t *>(t + B.base_off);
+    for (int si = 0; si < B.n_steps; ++si) {
+        int64_t items = 0;
+        for (int b = 0; b < n_beams; ++b) {
+            views[(int64_t)si * n_beams + b] =
+                beam_view(params, B, beams[b], b, si, static_cast<char *>(workspace));
+            base[(int64_t)si * (n_beams + 1) + b] = items;
+            items += (int64_t)beams[b].n_dm * B.L[b].steps[si].tiles;
+        }
+        base[(int64_t)si * (n_beams + 1) + n_beams] = items;
+    }
+    return SPD_OK;
+}
+
+int spd_batch_search(const spd_params *params, int32_t n_beams, const spd_beam *beams,
+                     const void *table_dev, void *workspace, int64_t workspace_bytes,
+                     int32_t grid, void *hip_stream) {
+    BatchPlan B;
+    int st = batch_plan(params, n_beams, beams, &B);
+    if (st != SPD_OK) return st;
+    if (!table_dev || grid < 0) return SPD_EINVAL;
+    if ((uintptr_t)table_dev & 15) return SPD_EALIGN;
+    if (!workspace || workspace_bytes < B.ws_total) return SPD_EWORKSPACE;
+    if ((uintptr_t)workspace & 255) return SPD_EALIGN;
+    for (int b = 0; b < n_beams; ++b) {
+        st = check_beam(params, B, beams[b], b);
+        if (st != SPD_OK) return st;
+    }
+    const char *t = static_cast<const char *>(table_dev);
+    for (int si = 0; si < B.n_steps; ++si) {
+        const StepPlan &sp = B.L[0].steps[si];
+        spd::StepBatchArgs a;
+        fill_step_shared(params, B.s, sp, si, &a.s);
+        a.beams = reinterpret_cast<const spd::BeamView *>(t) + (int64_t)si * n_beams;
+        a.item_base = reinterpret_cast<const int64_t *>(t + B.base_off) + (int64_t)si * (n_beams + 1);
+        a.n_beams = n_beams;
+        int64_t items = 0;
+        for (int b = 0; b < n_beams; ++b) items += (int64_t)beams[b].n_dm * B.L[b].steps[si].tiles;
+        a.n_items = items;
+        const int64_t g = grid > 0 ? std::min<int64_t>(grid, items) : std::min<int64_t>(items, INT32_MAX);
+        const int err = spd::launch_step_batch(a, B.s.fam, sp.lds_bytes, (int)g, hip_stream);
+        if (err) return hip_fail(err);
+    }
+    if (!(params->flags & SPD_WRITE_CANDIDATES)) return SPD_OK;
+    for (int b = 0; b < n_beams; ++b) {
+        Prepared P;
+        P.s = B.s;
+        P.L = B.L[b];
+        P.ws = static_cast<char *>(workspace) + B.ws_off[b];
+        const bool planes = params->flags & SPD_WRITE_PLANES;
+        P.Y = planes ? beams[b].snr : reinterpret_cast<float *>(P.ws + P.L.off_Y);
+        P.W = planes ? beams[b].width : reinterpret_cast<uint16_t *>(P.ws + P.L.off_W);
+        st = run_peaks(params, P, beams[b].n_dm, beams[b].t0, beams[b].cand, beams[b].cand_cap,
+                       beams[b].cand_count, hip_stream);
+        if (st != SPD_OK) return st;
+    }
+    return SPD_OK;
 }
 
 }  // extern "C"

@@ -72,6 +72,35 @@ struct StepArgs {
     float rtab[kStepMaxLevels][kMaxLevelWidths];   // 1/sqrt(base + U 2^k) at [j][U-1]
 };
 
+// The buffers and sizes of one beam in a cascade launch (a beam is a block of DM rows with its
+// own length; the levels, width patterns and tile length are shared by the launch).
+struct BeamView {
+    const float *in;
+    const float *cin;
+    float *out;
+    float *cout;
+    const float *mean;
+    const float *sigma;
+    float *Y;
+    uint16_t *W;
+    uint32_t *slab_cnt;
+    uint32_t *slab_ent;
+    int64_t ld_in, ld_cin, ld_out;
+    int32_t n_dm, n_in, in_len, n_tiles, vec_ok, pad0;
+    int64_t plane_off[kStepMaxLevels];
+    int64_t pitch[kStepMaxLevels];
+    int64_t slab_base[kStepMaxLevels];
+    int32_t slots[kStepMaxLevels];
+};
+
+struct StepBatchArgs {
+    StepArgs s;                 // shared fields (the per-beam ones are unused)
+    const BeamView *beams;      // [n_beams], device
+    const int64_t *item_base;   // [n_beams + 1], device: first work item of each beam
+    int64_t n_items;
+    int32_t n_beams;
+};
+
 struct ExhArgs {
     const float *x;
     int64_t ld;
@@ -137,6 +166,7 @@ struct PeakArgs {
 int launch_scales(const ScaleArgs &a, void *stream);
 int launch_evalmask(const MaskArgs &a, void *stream);
 int launch_step(const StepArgs &a, int fam, int lds_bytes, void *stream);
+int launch_step_batch(const StepBatchArgs &a, int fam, int lds_bytes, int grid, void *stream);
 // unit-count mask of a family's compiled-in pattern (1 or 2); families: 1-3 IG(1..3),
 // 4-6 BD-8/16/32, 7 DIT, 0 none
 uint64_t family_mask(int fam, int pattern);

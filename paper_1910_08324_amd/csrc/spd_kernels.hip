@@ -175,35 +175,84 @@ __device__ __forceinline__ void bank_generic(const float *y, const float *rt, in
     }
 }
 
-template <bool FIRST, int FAM>
-__global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(const StepArgs A) {
-    extern __shared__ float lds[];
-    __shared__ uint32_t st_cnt[kStepMaxLevels];
+// Where a tile finds its beam's buffers and sizes: in the launch arguments (one beam per
+// launch) or in a table in device memory (many beams per launch).
+struct ArgGeom {
+    const StepArgs &A;
+    __device__ const float *in() const { return A.in; }
+    __device__ const float *cin() const { return A.cin; }
+    __device__ float *out() const { return A.out; }
+    __device__ float *cout() const { return A.cout; }
+    __device__ const float *mean() const { return A.mean; }
+    __device__ const float *sigma() const { return A.sigma; }
+    __device__ float *Y() const { return A.Y; }
+    __device__ uint16_t *W() const { return A.W; }
+    __device__ uint32_t *slab_cnt() const { return A.slab_cnt; }
+    __device__ uint32_t *slab_ent() const { return A.slab_ent; }
+    __device__ int64_t ld_in() const { return A.ld_in; }
+    __device__ int64_t ld_cin() const { return A.ld_cin; }
+    __device__ int64_t ld_out() const { return A.ld_out; }
+    __device__ int n_in() const { return A.n_in; }
+    __device__ int in_len() const { return A.in_len; }
+    __device__ int n_tiles() const { return A.n_tiles; }
+    __device__ int vec_ok() const { return A.vec_ok; }
+    __device__ int64_t plane_off(int j) const { return A.lv[j].plane_off; }
+    __device__ int64_t pitch(int j) const { return A.lv[j].pitch; }
+    __device__ int64_t slab_base(int j) const { return A.lv[j].slab_base; }
+    __device__ int slots(int j) const { return A.lv[j].slots; }
+};
 
+struct TabGeom {
+    const BeamView *V;
+    __device__ const float *in() const { return V->in; }
+    __device__ const float *cin() const { return V->cin; }
+    __device__ float *out() const { return V->out; }
+    __device__ float *cout() const { return V->cout; }
+    __device__ const float *mean() const { return V->mean; }
+    __device__ const float *sigma() const { return V->sigma; }
+    __device__ float *Y() const { return V->Y; }
+    __device__ uint16_t *W() const { return V->W; }
+    __device__ uint32_t *slab_cnt() const { return V->slab_cnt; }
+    __device__ uint32_t *slab_ent() const { return V->slab_ent; }
+    __device__ int64_t ld_in() const { return V->ld_in; }
+    __device__ int64_t ld_cin() const { return V->ld_cin; }
+    __device__ int64_t ld_out() const { return V->ld_out; }
+    __device__ int n_in() const { return V->n_in; }
+    __device__ int in_len() const { return V->in_len; }
+    __device__ int n_tiles() const { return V->n_tiles; }
+    __device__ int vec_ok() const { return V->vec_ok; }
+    __device__ int64_t plane_off(int j) const { return V->plane_off[j]; }
+    __device__ int64_t pitch(int j) const { return V->pitch[j]; }
+    __device__ int64_t slab_base(int j) const { return V->slab_base[j]; }
+    __device__ int slots(int j) const { return V->slots[j]; }
+};
+
+// One tile (DM row d, tile `tile`) of a cascade launch.  A holds what every beam of the launch
+// shares (levels, width patterns, tile length); G the beam's buffers and sizes.
+template <bool FIRST, int FAM, class G>
+__device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const int d,
+                                          const int tile, float *lds, uint32_t *st_cnt) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int d = blockIdx.x / A.n_tiles;
-    const int tile = blockIdx.x - d * A.n_tiles;
-    if (d >= A.n_dm) return;
     const int T = A.T;
     const int64_t u0 = (int64_t)tile * T;
     if (tid < kStepMaxLevels) st_cnt[tid] = 0;
 
     // ---- 1. window of the input series (normalised in the first step) and carried prefixes
     {
-        const float *inr = A.in + (int64_t)d * A.ld_in;
+        const float *inr = V.in() + (int64_t)d * V.ld_in();
         float mu = 0.0f, inv = 1.0f;
         if (FIRST) {
-            mu = A.mean[d];
-            inv = 1.0f / A.sigma[d];
+            mu = V.mean()[d];
+            inv = 1.0f / V.sigma()[d];
         }
         const int N0 = A.lv[0].n_units;
         float *y0 = lds + A.lv[0].lds_y;
-        const int64_t len = A.in_len;
+        const int64_t len = V.in_len();
         for (int i = tid * 4; i < N0; i += kStepThreads * 4) {
             const int64_t r = u0 + i;
             float4 v;
-            if (A.vec_ok && r + 3 < len) {
+            if (V.vec_ok() && r + 3 < len) {
                 v = *reinterpret_cast<const float4 *>(inr + r);
                 if (FIRST) {
                     v.x = (v.x - mu) * inv;
@@ -222,12 +271,12 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(con
             }
             *reinterpret_cast<float4 *>(y0 + i) = v;
         }
-        if (!FIRST && A.carry && A.cin) {
-            const float *cr = A.cin + (int64_t)d * A.ld_cin;
+        if (!FIRST && A.carry && V.cin()) {
+            const float *cr = V.cin() + (int64_t)d * V.ld_cin();
             float *c0 = lds + A.lv[0].lds_c;
             for (int i = tid; i < T; i += kStepThreads) {
                 const int64_t m = u0 + i;
-                c0[i] = (m < A.lv[0].slots) ? cr[m] : 0.0f;
+                c0[i] = (m < V.slots(0)) ? cr[m] : 0.0f;
             }
         }
     }
@@ -252,25 +301,25 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(con
         const int ngroups = Sj / kGroup;
         const float *yj = ybuf;
         const float *cj = cbuf;
-        const bool has_carry = A.carry && (j > 0 || A.cin != nullptr);
+        const bool has_carry = A.carry && (j > 0 || V.cin() != nullptr);
         const bool to_lds = A.carry && (j + 1 < A.J);
         const bool to_glb = A.carry && (j + 1 == A.J) && A.has_out;
-        float *cg = to_glb ? A.cout + (int64_t)d * A.ld_out + (int64_t)tile * (T >> A.J) : nullptr;
+        float *cg = to_glb ? V.cout() + (int64_t)d * V.ld_out() + (int64_t)tile * (T >> A.J) : nullptr;
         const bool sync_batches = form_next || to_lds;   // a batch writes into the live buffers
         const int k = L.k;
         const int umax = L.umax;
         const int base = L.base;
         const int pat = L.pattern;
         const float *rt = A.rtab[j];
-        float *rowY = A.Y + L.plane_off + (int64_t)d * L.pitch;
-        uint16_t *rowW = A.W + L.plane_off + (int64_t)d * L.pitch;
+        float *rowY = V.Y() + V.plane_off(j) + (int64_t)d * V.pitch(j);
+        uint16_t *rowW = V.W() + V.plane_off(j) + (int64_t)d * V.pitch(j);
         // a group is "fast" when the widest boxcar of its last slot ends inside the data
-        const int64_t fast_lim = (int64_t)A.n_in - base - ((int64_t)umax << k);
+        const int64_t fast_lim = (int64_t)V.n_in() - base - ((int64_t)umax << k);
         for (int gb = 0; gb < ngroups; gb += kStepThreads) {
             const int g = gb + tid;
             const int m0 = g * kGroup;
             const int ma = ms0 + m0;
-            const bool act = (g < ngroups) && (ma < L.slots);
+            const bool act = (g < ngroups) && (ma < V.slots(j));
             float best[kGroup];
             int bu[kGroup];
 #pragma unroll
@@ -303,7 +352,7 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(con
                 } else {
                     int64_t room[kGroup];
 #pragma unroll
-                    for (int q = 0; q < kGroup; ++q) room[q] = (int64_t)A.n_in - ((int64_t)(ma + q) << k);
+                    for (int q = 0; q < kGroup; ++q) room[q] = (int64_t)V.n_in() - ((int64_t)(ma + q) << k);
                     bank_generic(yj + m0, rt, umax, L.evalmask, L.ufull, k, base, room, X, Xc, best, bu);
                 }
                 if (cg) {
@@ -314,7 +363,7 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(con
                 int bw[kGroup];
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) bw[q] = bu[q] ? base + (bu[q] << k) : 0;
-                if (ma + kGroup <= L.slots) {
+                if (ma + kGroup <= V.slots(j)) {
                     *reinterpret_cast<float4 *>(rowY + ma) = make_float4(best[0], best[1], best[2], best[3]);
                     *reinterpret_cast<uint2 *>(rowW + ma) =
                         make_uint2((uint32_t)bw[0] | ((uint32_t)bw[1] << 16),
@@ -322,7 +371,7 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(con
                 } else {
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q)
-                        if (ma + q < L.slots) {
+                        if (ma + q < V.slots(j)) {
                             rowY[ma + q] = best[q];
                             rowW[ma + q] = (uint16_t)bw[q];
                         }
@@ -343,18 +392,18 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(con
                     for (int q = 0; q < kGroup; ++q) {
                         const float l = q > 0 ? best[q - 1] : left;
                         const float rr = q + 1 < kGroup ? best[q + 1] : right;
-                        hit[q] = act && (ma + q < L.slots) && best[q] > A.threshold &&
+                        hit[q] = act && (ma + q < V.slots(j)) && best[q] > A.threshold &&
                                  best[q] > l && best[q] >= rr;
                         nh += hit[q];
                     }
                     if (nh) {
-                        const int64_t slab = L.slab_base + (int64_t)d * A.n_tiles + tile;
+                        const int64_t slab = V.slab_base(j) + (int64_t)d * V.n_tiles() + tile;
                         uint32_t pos = atomicAdd(&st_cnt[j], (uint32_t)nh);
 #pragma unroll
                         for (int q = 0; q < kGroup; ++q) {
                             if (hit[q]) {
                                 if (pos < (uint32_t)kSlabCap)
-                                    A.slab_ent[slab * kSlabCap + pos] = (uint32_t)(ma + q);
+                                    V.slab_ent()[slab * kSlabCap + pos] = (uint32_t)(ma + q);
                                 ++pos;
                             }
                         }
@@ -388,12 +437,43 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(con
     // ---- 4. hand on the last formed level
     if (A.has_out) {
         const float *yJ = lds + A.lv[0].lds_y;
-        float *o = A.out + (int64_t)d * A.ld_out + (int64_t)tile * (T >> A.J);
+        float *o = V.out() + (int64_t)d * V.ld_out() + (int64_t)tile * (T >> A.J);
         for (int n = tid; n < (T >> A.J); n += kStepThreads) o[n] = yJ[n];
     }
     if (A.want_cand) {
         lds_barrier();
-        if (tid < A.J) A.slab_cnt[A.lv[tid].slab_base + (int64_t)d * A.n_tiles + tile] = st_cnt[tid];
+        if (tid < A.J) V.slab_cnt()[V.slab_base(tid) + (int64_t)d * V.n_tiles() + tile] = st_cnt[tid];
+    }
+}
+
+
+// One launch for one beam: work-group = (DM row, tile).
+template <bool FIRST, int FAM>
+__global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(const StepArgs A) {
+    extern __shared__ float lds[];
+    __shared__ uint32_t st_cnt[kStepMaxLevels];
+    const int d = blockIdx.x / A.n_tiles;
+    const int tile = blockIdx.x - d * A.n_tiles;
+    if (d >= A.n_dm) return;
+    step_tile<FIRST, FAM>(A, ArgGeom{A}, d, tile, lds, st_cnt);
+}
+
+// One launch for many beams (same levels and tile length, any sizes): a persistent grid walks
+// the work items (beam, DM row, tile) in order; item i belongs to the beam b with
+// item_base[b] <= i < item_base[b + 1].
+template <bool FIRST, int FAM>
+__global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel_batch(const StepBatchArgs B) {
+    extern __shared__ float lds[];
+    __shared__ uint32_t st_cnt[kStepMaxLevels];
+    int b = 0;
+    for (int64_t item = blockIdx.x; item < B.n_items; item += gridDim.x) {
+        while (b + 1 < B.n_beams && B.item_base[b + 1] <= item) ++b;
+        const TabGeom V{B.beams + b};
+        const int64_t local = item - B.item_base[b];
+        const int d = (int)(local / V.n_tiles());
+        const int tile = (int)(local - (int64_t)d * V.n_tiles());
+        if (item != (int64_t)blockIdx.x) lds_barrier();   // the previous item is done with LDS
+        step_tile<FIRST, FAM>(B.s, V, d, tile, lds, st_cnt);
     }
 }
 
@@ -855,6 +935,32 @@ static int launch_step_fam(const StepArgs &a, int fam, int lds_bytes, hipStream_
         case 7: return launch_one<FIRST, 7>(a, lds_bytes, st);
         default: return launch_one<FIRST, 0>(a, lds_bytes, st);
     }
+}
+
+template <bool FIRST, int FAM>
+static int launch_batch(const StepBatchArgs &a, int lds_bytes, int grid, hipStream_t st) {
+    hipLaunchKernelGGL((step_kernel_batch<FIRST, FAM>), dim3((unsigned)grid), dim3(kStepThreads),
+                       lds_bytes, st, a);
+    return (int)hipGetLastError();
+}
+
+template <bool FIRST>
+static int launch_batch_fam(const StepBatchArgs &a, int fam, int lds_bytes, int grid, hipStream_t st) {
+    switch (fam) {
+        case 1: return launch_batch<FIRST, 1>(a, lds_bytes, grid, st);
+        case 2: return launch_batch<FIRST, 2>(a, lds_bytes, grid, st);
+        case 3: return launch_batch<FIRST, 3>(a, lds_bytes, grid, st);
+        case 4: return launch_batch<FIRST, 4>(a, lds_bytes, grid, st);
+        case 5: return launch_batch<FIRST, 5>(a, lds_bytes, grid, st);
+        case 6: return launch_batch<FIRST, 6>(a, lds_bytes, grid, st);
+        case 7: return launch_batch<FIRST, 7>(a, lds_bytes, grid, st);
+        default: return launch_batch<FIRST, 0>(a, lds_bytes, grid, st);
+    }
+}
+
+int launch_step_batch(const StepBatchArgs &a, int fam, int lds_bytes, int grid, void *stream) {
+    if (a.s.normalise) return launch_batch_fam<true>(a, fam, lds_bytes, grid, (hipStream_t)stream);
+    return launch_batch_fam<false>(a, fam, lds_bytes, grid, (hipStream_t)stream);
 }
 
 int launch_step(const StepArgs &a, int fam, int lds_bytes, void *stream) {

@@ -21,7 +21,7 @@ EXHAUSTIVE, BOXDIT, IGRID = 0, 1, 2
 WRITE_PLANES, WRITE_CANDIDATES = 1, 2
 MAX_LEVELS = 24
 MAX_LAUNCHES = 26
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class Params(ctypes.Structure):
@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
         ("threshold", ctypes.c_float),
         ("flags", ctypes.c_uint32),
         ("segment", ctypes.c_int32),
+        ("step_levels", ctypes.c_int32),
     ]
 
 
@@ -134,6 +135,7 @@ class Config:
     igrid_depth: Optional[int] = None
     igrid_layers: int = 0
     segment: int = 0
+    step_levels: int = 0
 
     def params(self) -> Tuple[Params, list]:
         keep = []
@@ -143,6 +145,7 @@ class Config:
         p.threshold = float(self.threshold)
         p.flags = (WRITE_PLANES if self.planes else 0) | (WRITE_CANDIDATES if self.candidates else 0)
         p.segment = int(self.segment)
+        p.step_levels = int(self.step_levels)
         if m in ("exh", "exhaustive"):
             p.method = EXHAUSTIVE
             if self.widths is not None:
@@ -359,3 +362,93 @@ class Runner:
                                     self.t0, self._mu, self._sg, self._Y, self._W, self._C,
                                     self.cap, self._N, self._ws, self.workspace.numel(), self._s),
                "spd_search")
+
+
+# ---------------------------------------------------------------------------------------
+# Batches of beams (include/spd_batch.h)
+# ---------------------------------------------------------------------------------------
+class Beam(ctypes.Structure):
+    _fields_ = [
+        ("x", ctypes.c_void_p), ("ld", ctypes.c_int64),
+        ("n_dm", ctypes.c_int32), ("n_in", ctypes.c_int32), ("n_out", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("t0", ctypes.c_int64),
+        ("mean", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+        ("snr", ctypes.c_void_p), ("width", ctypes.c_void_p),
+        ("cand", ctypes.c_void_p), ("cand_cap", ctypes.c_int64), ("cand_count", ctypes.c_void_p),
+    ]
+
+
+def _bind_batch(lib):
+    if getattr(lib, "_batch_bound", False):
+        return lib
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.spd_batch_plan.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(Beam),
+                                   ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.spd_batch_table.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(Beam), P, P, i64]
+    lib.spd_batch_search.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(Beam), P, P, i64,
+                                     i32, P]
+    for n in ("spd_batch_plan", "spd_batch_table", "spd_batch_search"):
+        getattr(lib, n).restype = ctypes.c_int
+    lib._batch_bound = True
+    return lib
+
+
+class Batch:
+    """Many beams searched with one parameter set: one fused launch per cascade step.
+
+    beams: list of (x [n_dm, ld] float32, mean [n_dm], sigma [n_dm]) device tensors.  Output
+    planes (with cfg.planes) and candidate buffers are allocated here, one Result per beam.
+    `grid` is the persistent grid of the cascade launches (0: one work-group per item)."""
+
+    def __init__(self, beams, cfg: Config, cand_cap: int = 1 << 20, grid: int = 0, stream=None):
+        import torch
+        self.cfg = cfg
+        self.grid = int(grid)
+        self.params, self._keep = cfg.params()
+        lib = _bind_batch(load())
+        self._lib = lib
+        n = len(beams)
+        self.arr = (Beam * n)()
+        self.results: List[Result] = []
+        self.inputs = beams
+        dev = beams[0][0].device
+        for i, (x, mu, sg) in enumerate(beams):
+            n_dm, n_in = x.shape
+            info = plan(cfg, n_dm, n_in)
+            snr = width = cand = count = None
+            if cfg.planes:
+                snr = torch.empty(int(info.plane_elems), dtype=torch.float32, device=dev)
+                width = torch.empty(int(info.plane_elems), dtype=torch.int16, device=dev)
+            if cfg.candidates:
+                cand = torch.empty(max(1, cand_cap) * CANDIDATE_DTYPE.itemsize, dtype=torch.uint8,
+                                   device=dev)
+                count = torch.zeros(1, dtype=torch.int64, device=dev)
+            self.results.append(Result(info, snr, width, cand, count, n_dm))
+            b = self.arr[i]
+            b.x, b.ld = x.data_ptr(), x.stride(0)
+            b.n_dm, b.n_in, b.n_out, b.t0 = n_dm, n_in, n_in, 0
+            b.mean, b.sigma = mu.data_ptr(), sg.data_ptr()
+            b.snr = snr.data_ptr() if snr is not None else None
+            b.width = width.data_ptr() if width is not None else None
+            b.cand = cand.data_ptr() if cand is not None else None
+            b.cand_cap = cand_cap if cfg.candidates else 0
+            b.cand_count = count.data_ptr() if count is not None else None
+        wsb, tb = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.spd_batch_plan(ctypes.byref(self.params), n, self.arr, ctypes.byref(wsb),
+                                  ctypes.byref(tb)), "spd_batch_plan")
+        self.workspace = torch.empty(int(wsb.value), dtype=torch.uint8, device=dev)
+        host = np.zeros(int(tb.value), dtype=np.uint8)
+        _check(lib.spd_batch_table(ctypes.byref(self.params), n, self.arr,
+                                   ctypes.c_void_p(self.workspace.data_ptr()),
+                                   host.ctypes.data_as(ctypes.c_void_p), int(tb.value)),
+               "spd_batch_table")
+        self.table = torch.from_numpy(host).to(dev)
+        self.stream = torch.cuda.current_stream(dev).cuda_stream if stream is None else stream
+
+    def search(self):
+        _check(self._lib.spd_batch_search(ctypes.byref(self.params), len(self.results), self.arr,
+                                          ctypes.c_void_p(self.table.data_ptr()),
+                                          ctypes.c_void_p(self.workspace.data_ptr()),
+                                          self.workspace.numel(), self.grid,
+                                          ctypes.c_void_p(self.stream)), "spd_batch_search")
+

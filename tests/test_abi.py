@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib):
                           "spd_prop_adam", "spd_tile_max", "spd_prop_labels"}
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.spd_abi_version() == spd.ABI_VERSION == 2
+    assert lib.spd_abi_version() == spd.ABI_VERSION == 3
 
 
 CASES = [("exh", 1), ("exh", 256), ("exh", 8192), ("dit", 8192)] + \
@@ -219,3 +219,54 @@ def test_proposal_pack_roundtrip(lib):
     assert u["W1"].shape == (32, 5, 5) and u["W2"].shape == (32, 5, 32)
     W1 = v[:1280].reshape(32, 5, 8)
     assert np.all(W1[:, :, 5:] == 0)
+
+
+@pytest.mark.parametrize("method", ["ig1", "ig3", "bd16", "dit"])
+def test_step_levels_controls_launch_depth(lib, method):
+    base = spd.plan(spd.Config(method, 8192), 4, 262144)
+    for J in (1, 2, 3, 4, 5, 6):
+        info = spd.plan(spd.Config(method, 8192, step_levels=J), 4, 262144)
+        levels = [info.launch_levels[i] for i in range(info.n_launches)]
+        assert sum(levels) == base.n_levels and max(levels) <= J
+        assert [info.plane_slots[i] for i in range(info.n_levels)] == \
+            [base.plane_slots[i] for i in range(base.n_levels)]
+    with pytest.raises(spd.SpdError):
+        spd.plan(spd.Config(method, 8192, step_levels=7), 4, 1000)
+    with pytest.raises(spd.SpdError):
+        spd.plan(spd.Config("exh", 100, step_levels=2), 4, 1000)
+
+
+def test_batch_plan_and_table_host(lib):
+    """Batch planning and the descriptor table on the host (no device work)."""
+    import numpy as np
+    L = spd._bind_batch(lib)
+    shapes = [(3, 20011), (5, 9000), (2, 40000)]
+    arr = (spd.Beam * len(shapes))()
+    for i, (n_dm, n) in enumerate(shapes):
+        arr[i].x, arr[i].ld, arr[i].n_dm, arr[i].n_in, arr[i].n_out = 4096, n, n_dm, n, n
+        arr[i].mean = arr[i].sigma = 4096
+    p, keep = spd.Config("ig1", 700).params()
+    wsb, tb = ctypes.c_int64(), ctypes.c_int64()
+    assert L.spd_batch_plan(ctypes.byref(p), len(shapes), arr, ctypes.byref(wsb), ctypes.byref(tb)) == 0
+    total = sum(spd.plan(spd.Config("ig1", 700), n_dm, n).workspace_bytes for n_dm, n in shapes)
+    assert wsb.value >= total and tb.value > 0
+    host = np.zeros(tb.value, np.uint8)
+    assert L.spd_batch_table(ctypes.byref(p), len(shapes), arr, ctypes.c_void_p(1 << 20),
+                             host.ctypes.data_as(ctypes.c_void_p), tb.value) == 0
+    info = spd.plan(spd.Config("ig1", 700), 3, 20011)
+    steps = info.n_launches
+    base = host[-steps * (len(shapes) + 1) * 8:].view(np.int64).reshape(steps, len(shapes) + 1)
+    for si in range(steps):
+        items = [0]
+        for n_dm, n in shapes:
+            inf = spd.plan(spd.Config("ig1", 700), n_dm, n)
+            tiles = inf.n_segments if si == 0 else None
+            items.append(items[-1] + (n_dm * tiles if tiles is not None else 0))
+        assert base[si, 0] == 0 and np.all(np.diff(base[si]) > 0)
+        if si == 0:
+            assert list(base[0]) == items
+    pe, keep2 = spd.Config("exh", 100).params()
+    assert L.spd_batch_plan(ctypes.byref(pe), 1, arr, ctypes.byref(wsb), ctypes.byref(tb)) == spd.SPD_EINVAL
+    assert L.spd_batch_plan(ctypes.byref(p), 0, arr, ctypes.byref(wsb), ctypes.byref(tb)) == spd.SPD_EINVAL
+    assert L.spd_batch_search(ctypes.byref(p), len(shapes), arr, None, ctypes.c_void_p(256),
+                              wsb.value, 0, None) == spd.SPD_EINVAL

@@ -1,0 +1,131 @@
+"""GPU tests of the batched search (include/spd_batch.h) and the autotuner: every beam of a
+fused multi-beam launch gives bitwise the planes and candidates of spd_search on that beam
+alone, whatever the persistent grid, tile length or on-chip depth; one beam is also checked
+against the FP64 oracle directly."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import planes as oplanes, widths as ow
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def spd():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    from paper_1910_08324_amd import spd as m
+    m.load()
+    return m
+
+
+SHAPES = [(3, 20011), (5, 9000), (2, 40000), (7, 4096), (1, 1000)]
+
+
+def make_beams(seed=0, shapes=SHAPES):
+    beams, host = [], []
+    for i, (n_dm, n) in enumerate(shapes):
+        rng = np.random.default_rng(seed + i)
+        x = synth.noise_rows(n, seed * 100 + i, range(n_dm))
+        mu = rng.uniform(-0.5, 0.5, n_dm).astype(np.float32)
+        sg = rng.uniform(0.8, 1.5, n_dm).astype(np.float32)
+        x = (x * sg[:, None] + mu[:, None]).astype(np.float32)
+        p = synth.Pulse(n_dm - 1, n // 3, 40, 14.0, "gauss")
+        x[p.dm, p.start:p.start + p.width] += (synth.pulse_profile(p) * sg[p.dm]).astype(np.float32)
+        host.append((x, mu, sg))
+        beams.append(tuple(torch.from_numpy(a).cuda() for a in (x, mu, sg)))
+    return beams, host
+
+
+def single(spd, beam, cfg):
+    x, mu, sg = beam
+    r = spd.search(x, mu, sg, cfg, cand_cap=1 << 16)
+    torch.cuda.synchronize()
+    return r
+
+
+def same_result(a, b, cfg, what):
+    if cfg.planes:
+        for la, lb in zip(a.planes_host(), b.planes_host()):
+            assert np.array_equal(la["Y"], lb["Y"]) and np.array_equal(la["W"], lb["W"]), what
+    if cfg.candidates:
+        assert np.array_equal(a.candidates_host(), b.candidates_host()), what
+
+
+@pytest.mark.parametrize("method", ["ig1", "ig3", "bd16", "bd8", "dit"])
+@pytest.mark.parametrize("grid", [0, 7])
+def test_batch_bitwise_equals_single_beams(spd, method, grid):
+    say(f"[batch] {method} grid {grid}")
+    beams, _ = make_beams()
+    cfg = spd.Config(method, 700, threshold=4.0)
+    b = spd.Batch(beams, cfg, cand_cap=1 << 16, grid=grid)
+    b.search()
+    torch.cuda.synchronize()
+    for i, beam in enumerate(beams):
+        same_result(b.results[i], single(spd, beam, cfg), cfg, (method, grid, i))
+
+
+def test_batch_candidates_only_and_repeat(spd):
+    beams, _ = make_beams(seed=3)
+    cfg = spd.Config("ig2", 1000, threshold=4.0, planes=False)
+    b = spd.Batch(beams, cfg, cand_cap=1 << 16, grid=13)
+    b.search()
+    b.search()                                   # the workspace is reused: same result again
+    torch.cuda.synchronize()
+    for i, beam in enumerate(beams):
+        same_result(b.results[i], single(spd, beam, cfg), cfg, i)
+
+
+def test_batch_beam_matches_oracle(spd):
+    beams, host = make_beams(seed=5, shapes=[(4, 12007), (3, 3001)])
+    cfg = spd.Config("bd8", 300, threshold=4.0)
+    b = spd.Batch(beams, cfg, cand_cap=1 << 16)
+    b.search()
+    torch.cuda.synchronize()
+    for i, (x, mu, sg) in enumerate(host):
+        R = oplanes.planes(x, mu, sg, ow.method_levels("bd8", 300))
+        parity.check_planes(b.results[i].planes_host(), R, x, mu, sg, x.shape[1], what=f"beam {i}")
+        parity.check_candidates(b.results[i].candidates_host(), R, 4.0, what=f"beam {i}")
+
+
+@pytest.mark.parametrize("method,segment,depth", [("ig1", 2048, 3), ("ig1", 8192, 4),
+                                                  ("bd16", 3072, 5), ("ig3", 6144, 6)])
+def test_launch_shape_does_not_change_results(spd, method, segment, depth):
+    beams, _ = make_beams(seed=7, shapes=[(3, 50000), (2, 17000)])
+    ref_cfg = spd.Config(method, 2000, threshold=4.0)
+    cfg = spd.Config(method, 2000, threshold=4.0, segment=segment, step_levels=depth)
+    b = spd.Batch(beams, cfg, cand_cap=1 << 16, grid=5)
+    b.search()
+    torch.cuda.synchronize()
+    for i, beam in enumerate(beams):
+        same_result(b.results[i], single(spd, beam, ref_cfg), cfg, (method, segment, depth, i))
+
+
+def test_autotuner_groups_and_matches(spd):
+    from paper_1910_08324_amd import autotune
+    say("[batch] autotuner")
+    tuner = autotune.Tuner(rows=64, reps=1)
+    beams, _ = make_beams(seed=9, shapes=[(6, 70000), (4, 30000), (5, 70001), (3, 200000)])
+    groups = autotune.tuned_batches(beams, "ig1", 1000, tuner, threshold=4.0, planes=True)
+    seen = sorted(i for idx, _ in groups for i in idx)
+    assert seen == list(range(len(beams)))
+    say(f"  groups {[(idx, b.cfg.segment, b.cfg.step_levels, b.grid) for idx, b in groups]}")
+    ref_cfg = spd.Config("ig1", 1000, threshold=4.0)
+    for idx, b in groups:
+        b.search()
+        torch.cuda.synchronize()
+        for k, i in enumerate(idx):
+            same_result(b.results[k], single(spd, beams[i], ref_cfg), ref_cfg, i)
+    c = tuner.choose("ig1", 1000, 70000)
+    assert c.segment in autotune.SEGMENTS and c.step_levels in autotune.DEPTHS
+    assert c.ms == min(m[2] for m in c.measured)
