@@ -162,11 +162,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample time")
     ap.add_argument("--segment", type=int, default=0, help="tile length override (0: library's)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's default launch shape instead of the autotuner's")
     ap.add_argument("--profile-probe", action="store_true")
     ap.add_argument("--proposal-tiles", type=int, default=65536,
                     help="tiles of 64 x 4096 to train the learned proposal on (0: skip)")
     ap.add_argument("--proposal-eval", type=int, default=8192, help="held-out evaluation tiles")
     ap.add_argument("--proposal-batch", type=int, default=256)
+    ap.add_argument("--batch-beams", type=int, default=32,
+                    help="beams of the batched multi-beam run (0: skip)")
+    ap.add_argument("--batch-dm-scale", type=int, default=8,
+                    help="divide the batched run's DM counts (512..4096) by this (1: full size)")
+    ap.add_argument("--batch-ws-gb", type=float, default=120.0, help="workspace budget per fused group")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -191,7 +198,24 @@ def main():
     sg = torch.ones(w.n_dm, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
-    cfg = spd.Config(args.method, w.l_end, threshold=w.threshold, segment=args.segment)
+    tuner = None
+    if not args.no_tune and args.segment == 0:
+        from paper_1910_08324_amd import autotune
+        tuner = autotune.Tuner(rows=w.n_dm, reps=2)
+
+    def config_for(method):
+        """The method's search config with the autotuner's launch shape for this beam shape."""
+        if tuner is None or method == "exh":
+            return spd.Config(method, w.l_end, threshold=w.threshold, segment=args.segment), None
+        t0 = time.time()
+        c = tuner.choose(method, w.l_end, w.n)
+        log(f"[bench] tuned {method}: segment {c.segment}, levels per launch {c.step_levels} "
+            f"({len(c.measured)} shapes, {time.time() - t0:.1f} s)")
+        return (spd.Config(method, w.l_end, threshold=w.threshold, segment=c.segment,
+                           step_levels=c.step_levels),
+                {"segment": c.segment, "step_levels": c.step_levels, "shapes": len(c.measured)})
+
+    cfg, tuned = config_for(args.method)
     run = spd.Runner(x, mu, sg, cfg, cand_cap=1 << 22)
     info = run.info
 
@@ -290,7 +314,7 @@ def main():
     if not args.no_exhaustive:
         others.append("exh")
     for m in others:
-        cfg_m = spd.Config(m, w.l_end, threshold=w.threshold)
+        cfg_m, tuned_m = config_for(m)
         r = spd.Runner(x, mu, sg, cfg_m, cand_cap=1 << 22)
         r.search()
         torch.cuda.synchronize()
@@ -313,6 +337,8 @@ def main():
         ent = {"ms": round(ms, 4), "rtf": round(w.n * T_SAMPLE / (ms * 1e-3), 2),
                "filter_ms": round(fms, 4)}
         ent["dominant"] = dominant_entry(m, cfg_m, r, w, n_rep)
+        if tuned_m:
+            ent["launch_shape"] = tuned_m
         methods[m] = ent
         log(f"[bench] {m}: {ms:.3f} ms/search (filter {fms:.3f} ms), RTF {ent['rtf']}, dominant "
             f"{ent['dominant']['kernel']} {ent['dominant']['ms']} ms: "
@@ -368,6 +394,11 @@ def main():
                          f"(FP64 oracle, {spent:.1f} s)"}
         log(f"[bench] cpu oracle: {cpu['value']:.3e} DM*samples/s on {cpu['cores']} threads")
 
+    batch = None
+    if args.batch_beams > 0:
+        torch.cuda.empty_cache()
+        batch = batch_section(args, dev)
+
     prop = None
     if args.proposal_tiles > 0:
         torch.cuda.empty_cache()
@@ -387,7 +418,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "method": args.method, "n_dm": w.n_dm, "n_samples": w.n,
-                   "tile": info.segment,
+                   "tile": info.segment, "levels_per_launch": max(int(info.launch_levels[i])
+                                                                  for i in range(info.n_launches)),
+                   "launch_shape": "autotuned" if tuned else "library default",
                    "l_end": w.l_end, "threshold": w.threshold, "t_sample_us": 64,
                    "outputs": "planes+candidates", "pulses": len(w.pulses)},
         "rtf": rtf,
@@ -403,9 +436,88 @@ def main():
         out["speedup_vs_exhaustive"] = rtf / methods["exh"]["rtf"]
     if "mean_loss" in methods.get(args.method, {}):
         out["mean_loss_vs_exhaustive"] = methods[args.method]["mean_loss"]
+    if batch is not None:
+        out["batch"] = batch
     if prop is not None:
         out["proposal"] = prop
     print(json.dumps(out), flush=True)
+
+
+def batch_section(args, dev) -> dict:
+    """Many beams with uneven DM counts and lengths: tuned fused multi-beam launches against the
+    same beams searched one by one (candidates only; planes live in the workspace)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1910_08324_amd import autotune, spd
+
+    rng = np.random.default_rng(11)
+    shapes = [(max(1, int(rng.integers(512, 4097)) // args.batch_dm_scale),
+               int(rng.integers(1 << 16, (1 << 19) + 1))) for _ in range(args.batch_beams)]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    beams = []
+    t = time.time()
+    for bi, (n_dm, n) in enumerate(shapes):
+        x = torch.randn((n_dm, n), generator=gen, device=dev, dtype=torch.float32)
+        # 16 Gaussian pulses per beam, FWHM 1..4096 log-uniform, SNR 5..50 (the beam's recipe)
+        for p in synth.draw_gauss_pulses(n_dm, n, min(16, n_dm), seed=1000 + bi):
+            prof = torch.from_numpy(synth.pulse_profile(p).astype(np.float32)).to(dev)
+            w = min(p.width, n - p.start)
+            x[p.dm, p.start:p.start + w] += prof[:w]
+        beams.append((x, torch.zeros(n_dm, device=dev), torch.ones(n_dm, device=dev)))
+    torch.cuda.synchronize()
+    samples = sum(a * b for a, b in shapes)
+    log(f"[bench] batch: {len(shapes)} beams, {samples * 4 / 2**30:.1f} GiB input, generated in "
+        f"{time.time() - t:.1f} s")
+    tuner = autotune.Tuner(rows=256, reps=2)
+    t = time.time()
+    groups = autotune.tuned_groups(beams, args.method, 8192, tuner, threshold=5.0,
+                                   max_workspace_bytes=int(args.batch_ws_gb * 2**30))
+    tune_s = time.time() - t
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fused_ms, desc = 0.0, []
+    for idx, cfg in groups:
+        b = spd.Batch([beams[i] for i in idx], cfg, cand_cap=1 << 20)
+        b.grid = autotune.tune_batch_grid(b)
+        b.search()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            b.search()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        fused_ms += ms
+        desc.append({"beams": len(idx), "segment": cfg.segment, "step_levels": cfg.step_levels,
+                     "grid": b.grid, "ms": round(ms, 3)})
+        del b
+        torch.cuda.empty_cache()
+    # the same beams one by one with the default launch shape
+    single_ms = 0.0
+    for x, mu, sg in beams:
+        r = spd.Runner(x, mu, sg, spd.Config(args.method, 8192, threshold=5.0, planes=False),
+                       cand_cap=1 << 20)
+        r.search()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            r.search()
+        e1.record()
+        torch.cuda.synchronize()
+        single_ms += e0.elapsed_time(e1) / 3
+        del r
+    torch.cuda.empty_cache()
+    log(f"[bench] batch: fused {fused_ms:.2f} ms ({samples / (fused_ms * 1e-3):.3e} DM*samples/s) "
+        f"vs one by one {single_ms:.2f} ms; groups {desc}; tuning {tune_s:.1f} s")
+    return {"beams": len(shapes), "dm_scale": args.batch_dm_scale,
+            "input_gib": round(samples * 4 / 2**30, 2), "samples": samples,
+            "method": args.method, "l_end": 8192, "outputs": "candidates",
+            "fused_ms": round(fused_ms, 3), "one_by_one_ms": round(single_ms, 3),
+            "fused_dm_samples_per_s": samples / (fused_ms * 1e-3),
+            "one_by_one_dm_samples_per_s": samples / (single_ms * 1e-3),
+            "groups": desc, "tuning_seconds": round(tune_s, 1),
+            "shapes": shapes}
 
 
 def proposal_section(args, dev) -> dict:

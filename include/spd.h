@@ -84,7 +84,7 @@ extern "C" {
  *                   every launch of the level cascade room for its halo and its on-chip buffers
  *                   (spd_plan returns SPD_EINVAL otherwise); exhaustive: 256 only.
  *   step_levels     BoxDIT / IGRID: separation levels computed on chip per kernel launch, 1..6,
- *                   or 0 for the library's choice (6, fewer if a tile's buffers would not fit).
+ *                   or 0 for the library's choice (4, fewer if a tile's buffers would not fit).
  *                   Results do not depend on it.  Exhaustive: must be 0.
  */
 typedef struct {
@@ -184,7 +184,7 @@ int spd_search(const spd_params *params, const float *x, int64_t ld, int32_t n_d
  * spd_filter: the boxcar search only (Sections 3.1 and 3.2): writes the planes (to snr/width,
  *   or into the workspace when SPD_WRITE_PLANES is not set) and, when SPD_WRITE_CANDIDATES is
  *   set, records in the workspace the slots above the threshold for spd_peaks.  BoxDIT and
- *   IGRID run as a chain of cascade launches, each computing up to six levels on chip and
+ *   IGRID run as a chain of cascade launches, each computing up to step_levels levels on chip and
  *   handing its last decimated series (and, for BoxDIT, the carried prefixes) to the next
  *   through the workspace; spd_plan_info lists them.  Arguments as for spd_search.
  * spd_peaks: candidate selection from the planes and records left by spd_filter (params->flags

@@ -91,6 +91,33 @@ class Tuner:
         return Choice(T, J, t, measured)
 
 
+def tuned_groups(beams: Sequence, method: str, l_end: int, tuner: Tuner, threshold: float = 5.0,
+                 planes: bool = False, candidates: bool = True,
+                 max_workspace_bytes: Optional[int] = None) -> List[Tuple[List[int], "spd.Config"]]:
+    """Group beams [(x, mean, sigma), ...] by tuned launch shape, and split groups so that a
+    group's workspace (planes included when only candidates are asked for) stays within
+    max_workspace_bytes.  Returns [(beam indices, config)]."""
+    shapes: Dict[Tuple[int, int], List[int]] = {}
+    for i, (x, _, _) in enumerate(beams):
+        c = tuner.choose(method, l_end, x.shape[1], device=x.device, threshold=threshold)
+        shapes.setdefault((c.segment, c.step_levels), []).append(i)
+    out = []
+    for (T, J), idx in shapes.items():
+        cfg = spd.Config(method, l_end, threshold=threshold, planes=planes, candidates=candidates,
+                         segment=T, step_levels=J)
+        cur, used = [], 0
+        for i in idx:
+            x = beams[i][0]
+            ws = int(spd.plan(cfg, x.shape[0], x.shape[1]).workspace_bytes)
+            if cur and max_workspace_bytes is not None and used + ws > max_workspace_bytes:
+                out.append((cur, cfg))
+                cur, used = [], 0
+            cur.append(i)
+            used += ws
+        out.append((cur, cfg))
+    return out
+
+
 def tuned_batches(beams: Sequence, method: str, l_end: int, tuner: Tuner, threshold: float = 5.0,
                   planes: bool = False, candidates: bool = True, cand_cap: int = 1 << 20,
                   tune_grid: bool = True) -> List[Tuple[List[int], "spd.Batch"]]:

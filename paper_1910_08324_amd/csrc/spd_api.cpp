@@ -169,6 +169,7 @@ int build_search(const spd_params *p, Search *s) {
 }
 
 constexpr int kGroupC = spd::kGroup;
+constexpr int kDefaultStepLevels = 4;
 
 // One launch of the cascade kernel: levels k0 .. k0+J-1 over tiles of T units of its input.
 struct StepPlan {
@@ -323,7 +324,10 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
         int T = fixed_T ? p->segment : 4096;
         if (T < 256 || T > 32768 || T % 256) return SPD_EINVAL;
         if (p->step_levels < 0 || p->step_levels > spd::kStepMaxLevels) return SPD_EINVAL;
-        const int jmax = p->step_levels ? p->step_levels : spd::kStepMaxLevels;
+        // library's choice of levels per launch: 4 (measured on MI355X: moving levels 4 and 5,
+        // whose tiles keep few threads busy, into the next launch beats the extra 1/16-sized
+        // hand-off through HBM for every compiled-in family)
+        const int jmax = p->step_levels ? p->step_levels : kDefaultStepLevels;
         int k0 = 0;
         int64_t in_len = n_in;
         while (k0 <= K) {

@@ -202,8 +202,13 @@ struct ArgGeom {
     __device__ int slots(int j) const { return A.lv[j].slots; }
 };
 
+// The table is read-only during a launch and every lane of a work-group reads the same entry,
+// so it is addressed in the constant address space: its fields load as scalar (SMEM) reads.
+typedef __attribute__((address_space(4))) const BeamView *ConstBeamPtr;
+typedef __attribute__((address_space(4))) const int64_t *ConstI64Ptr;
+
 struct TabGeom {
-    const BeamView *V;
+    ConstBeamPtr V;
     __device__ const float *in() const { return V->in; }
     __device__ const float *cin() const { return V->cin; }
     __device__ float *out() const { return V->out; }
@@ -465,11 +470,13 @@ template <bool FIRST, int FAM>
 __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel_batch(const StepBatchArgs B) {
     extern __shared__ float lds[];
     __shared__ uint32_t st_cnt[kStepMaxLevels];
+    const ConstBeamPtr beams = (ConstBeamPtr)B.beams;
+    const ConstI64Ptr base = (ConstI64Ptr)B.item_base;
     int b = 0;
     for (int64_t item = blockIdx.x; item < B.n_items; item += gridDim.x) {
-        while (b + 1 < B.n_beams && B.item_base[b + 1] <= item) ++b;
-        const TabGeom V{B.beams + b};
-        const int64_t local = item - B.item_base[b];
+        while (b + 1 < B.n_beams && base[b + 1] <= item) ++b;
+        const TabGeom V{beams + b};
+        const int64_t local = item - base[b];
         const int d = (int)(local / V.n_tiles());
         const int tile = (int)(local - (int64_t)d * V.n_tiles());
         if (item != (int64_t)blockIdx.x) lds_barrier();   // the previous item is done with LDS
