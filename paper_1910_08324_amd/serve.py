@@ -1,0 +1,333 @@
+"""Streaming single-pulse search with continuous batching.
+
+Beams stream in as blocks of DM rows x samples (each block a device tensor, as a dedispersion
+stage on the same GPU would hand them over).  The server keeps each beam's recent samples on the
+device and, for every block, searches the next *region* of start times whose boxcars are now
+complete:
+
+    region [r0, r1):   r1 = largest multiple of 2^K with r1 + 2^K + L_end - 1 <= samples seen
+    window [t0, ...):  t0 = max(0, r0 - 2^K), through r1 + 2^K + L_end - 1
+    slots searched:    [t0, r1 + 2^K)  (one coarsest slot either side of the region)
+
+so every plane value in the region, and the time neighbours its 3x3 peak test reads, are those
+of a search over the whole stream: the candidates reported for a region (start in [r0, r1)) are
+exactly the whole-stream candidates there.  Regions start at multiples of 2^K (the coarsest
+boxcar spacing), as spd_search requires of t0.
+
+Continuous batching: requests (one per arriving block) wait in arrival order.  Whenever a
+batch slot is free, every waiting request whose beam has no search in flight, and whose memory
+fits the HBM budget beside what is already in flight, is admitted; the admitted windows run as
+ONE fused multi-beam search (spd_batch_search) on that slot's stream.  Several slots are in
+flight at once on separate streams, so requests that arrive while others run are admitted as
+slots and memory free up, and their work overlaps on the device.  A block's result depends only
+on its beam's stream, never on what it was batched with.
+
+Everything numeric runs in libspd's kernels; this module only sequences launches, copies and
+events.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes
+import dataclasses
+import time
+from typing import Deque, Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import spd
+
+
+@dataclasses.dataclass
+class Request:
+    beam: int
+    index: int                 # block number within the beam
+    block: "torch.Tensor"      # device [n_dm][B]
+    ready: Optional["torch.cuda.Event"]
+    arrival: float             # host time the block arrived
+    region: Tuple[int, int] = (0, 0)
+    mem: int = 0
+
+
+@dataclasses.dataclass
+class Result:
+    beam: int
+    index: int
+    region: Tuple[int, int]
+    candidates: np.ndarray     # spd.CANDIDATE_DTYPE, starts in region, (level, dm, start) order
+    arrival: float
+    done: float
+    total: int                 # candidates found in the searched window (before the region cut)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Beam:
+    def __init__(self, n_dm: int, cap: int, device, mean=None, sigma=None):
+        import torch
+        self.n_dm = n_dm
+        self.cap = cap
+        self.buf = [torch.zeros((n_dm, cap), dtype=torch.float32, device=device) for _ in range(2)]
+        self.active = 0
+        self.buf_start = 0         # absolute sample index of column 0 of the active buffer
+        self.t_end = 0             # samples received
+        self.r0 = 0                # next region start
+        self.busy = False
+        self.next_index = 0
+        self.mean = mean if mean is not None else torch.zeros(n_dm, device=device)
+        self.sigma = sigma if sigma is not None else torch.ones(n_dm, device=device)
+
+
+class _Slot:
+    def __init__(self, device, ws_bytes: int, table_bytes: int, max_reqs: int, cand_cap: int):
+        import torch
+        self.stream = torch.cuda.Stream(device=device)          # default priority
+        self.ws = torch.empty(max(256, ws_bytes), dtype=torch.uint8, device=device)
+        self.table_host = torch.empty(table_bytes, dtype=torch.uint8, pin_memory=True)
+        self.table_dev = torch.empty(table_bytes, dtype=torch.uint8, device=device)
+        self.cand = torch.empty((max_reqs, cand_cap * spd.CANDIDATE_DTYPE.itemsize),
+                                dtype=torch.uint8, device=device)
+        self.count = torch.zeros(max_reqs, dtype=torch.int64, device=device)
+        self.cand_host = torch.empty(tuple(self.cand.shape), dtype=torch.uint8, pin_memory=True)
+        self.count_host = torch.empty(max_reqs, dtype=torch.int64, pin_memory=True)
+        self.done = torch.cuda.Event()
+        self.reqs: List[Request] = []
+        self.busy = False
+        self.mem = 0
+
+
+class StreamServer:
+    """Continuous-batching server.  Use open_beam(), submit() blocks, and poll() (or drain())."""
+
+    def __init__(self, method: str = "ig1", l_end: int = 8192, threshold: float = 5.0,
+                 max_block: int = 8192, hbm_budget: int = 64 << 30, slots: int = 3,
+                 max_beams_per_batch: int = 16, cand_cap: int = 1 << 15, segment: int = 0,
+                 step_levels: int = 0, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        self.cfg = spd.Config(method, l_end, threshold=threshold, planes=False, candidates=True,
+                              segment=segment, step_levels=step_levels)
+        self.params, self._keep = self.cfg.params()
+        self.lib = spd._bind_batch(spd.load())
+        info = spd.plan(self.cfg, 1, 1 << 20)
+        self.grain = 1 << int(info.top_level)
+        self.l_end = int(l_end)
+        self.max_block = int(max_block)
+        # a window spans one grain before the region, the region (at most a block plus the
+        # grain of samples left over) and the look-ahead the last slots' boxcars need
+        self.cap = -(-(self.max_block + self.l_end + 4 * self.grain) // 64) * 64
+        self.budget = int(hbm_budget)
+        self.max_reqs = int(max_beams_per_batch)
+        self.cand_cap = int(cand_cap)
+        self.n_slots = int(slots)
+        self.slots: List[_Slot] = []
+        self.beams: Dict[int, _Beam] = {}
+        self.queue: Deque[Request] = collections.deque()
+        self.results: List[Result] = []
+        self.mem_in_flight = 0
+
+    # ------------------------------------------------------------------ set-up
+    def open_beam(self, beam: int, n_dm: int, mean=None, sigma=None):
+        self.beams[beam] = _Beam(n_dm, self.cap, self.device, mean, sigma)
+        if not self.slots:
+            self._make_slots(n_dm)
+
+    def _window_plan(self, n_dm: int, n_in: int, n_out: int) -> int:
+        return int(spd.plan(self.cfg, n_dm, n_in, n_out).workspace_bytes)
+
+    def _make_slots(self, n_dm: int):
+        # size every slot for a full batch of the largest windows
+        n_in = self.cap
+        per = self._window_plan(n_dm, n_in, n_in) + 4096
+        arr = (spd.Beam * self.max_reqs)()
+        for i in range(self.max_reqs):
+            arr[i].x, arr[i].ld, arr[i].n_dm, arr[i].n_in, arr[i].n_out = 256, n_in, n_dm, n_in, n_in
+            arr[i].mean = arr[i].sigma = 256
+        wsb, tb = ctypes.c_int64(), ctypes.c_int64()
+        spd._check(self.lib.spd_batch_plan(ctypes.byref(self.params), self.max_reqs, arr,
+                                           ctypes.byref(wsb), ctypes.byref(tb)), "spd_batch_plan")
+        for _ in range(self.n_slots):
+            self.slots.append(_Slot(self.device, int(wsb.value) + per, int(tb.value) + 4096,
+                                    self.max_reqs, self.cand_cap))
+
+    # ------------------------------------------------------------------ requests
+    def submit(self, beam: int, block, ready=None, arrival: Optional[float] = None):
+        """Queue one block (device [n_dm][B], B <= max_block) of a beam; `ready` is an event after
+        which the block's data is valid (the producer's stream)."""
+        b = self.beams[beam]
+        if block.shape[0] != b.n_dm or block.shape[1] > self.max_block:
+            raise ValueError("block shape does not match the beam")
+        r = Request(beam, b.next_index, block, ready, time.perf_counter() if arrival is None else arrival)
+        b.next_index += 1
+        self.queue.append(r)
+        return r
+
+    def _region(self, b: _Beam, t_end: int) -> Tuple[int, int]:
+        g = self.grain
+        r1 = ((t_end - self.l_end + 1 - g) // g) * g
+        return b.r0, max(b.r0, r1)
+
+    def _mem_of(self, b: _Beam, region) -> int:
+        r0, r1 = region
+        if r1 <= r0:
+            return 0
+        t0 = max(0, r0 - self.grain)
+        n_out = r1 + self.grain - t0
+        n_in = min(b.t_end, r1 + self.grain + self.l_end - 1) - t0
+        return self._window_plan(b.n_dm, n_in, n_out)
+
+    # ------------------------------------------------------------------ engine
+    def poll(self) -> int:
+        """Retire finished batches and admit waiting requests; returns the number retired."""
+        n = 0
+        for s in self.slots:
+            if s.busy and s.done.query():
+                self._retire(s)
+                n += 1
+        self._admit()
+        return n
+
+    def drain(self):
+        while self.queue or any(s.busy for s in self.slots):
+            if self.poll() == 0:
+                time.sleep(20e-6)
+
+    def _retire(self, s: _Slot):
+        now = time.perf_counter()
+        counts = s.count_host.numpy()
+        for i, r in enumerate(s.reqs):
+            b = self.beams[r.beam]
+            b.busy = False
+            total = int(counts[i]) if r.region[1] > r.region[0] else 0
+            if total > self.cand_cap:
+                raise RuntimeError(f"beam {r.beam} block {r.index}: {total} candidates exceed "
+                                   f"the capacity {self.cand_cap}")
+            c = s.cand_host[i, : total * spd.CANDIDATE_DTYPE.itemsize].numpy().view(spd.CANDIDATE_DTYPE)
+            keep = (c["start"] >= r.region[0]) & (c["start"] < r.region[1])
+            self.results.append(Result(r.beam, r.index, r.region, c[keep].copy(), r.arrival, now, total))
+        self.mem_in_flight -= s.mem
+        s.reqs, s.busy, s.mem = [], False, 0
+
+    def _admit(self):
+        import torch
+        while self.queue:
+            slot = next((s for s in self.slots if not s.busy), None)
+            if slot is None:
+                return
+            picked: List[Request] = []
+            taken = set()
+            mem = 0
+            for r in list(self.queue):
+                if len(picked) >= self.max_reqs:
+                    break
+                b = self.beams[r.beam]
+                if b.busy or r.beam in taken:
+                    taken.add(r.beam)            # keep each beam's blocks in order
+                    continue
+                region = self._region(b, b.t_end + r.block.shape[1])
+                need = self._mem_of_after(b, r, region)
+                if self.mem_in_flight + mem + need > self.budget:
+                    break                        # first come, first served within the budget
+                r.region, r.mem = region, need
+                picked.append(r)
+                taken.add(r.beam)
+                mem += need
+            if not picked:
+                return
+            for r in picked:
+                self.queue.remove(r)
+            self._launch(slot, picked, mem)
+
+    def _mem_of_after(self, b: _Beam, r: Request, region) -> int:
+        saved = b.t_end
+        b.t_end = saved + r.block.shape[1]
+        m = self._mem_of(b, region)
+        b.t_end = saved
+        return m
+
+    def _append(self, b: _Beam, block, stream):
+        """Copy a block after the beam's samples, first moving the samples the next window still
+        needs to the front of the other buffer if the active one is full."""
+        import torch
+        B = block.shape[1]
+        keep_from = max(0, b.r0 - self.grain)
+        if b.t_end + B - b.buf_start > b.cap:
+            src, dst = b.buf[b.active], b.buf[1 - b.active]
+            n = b.t_end - keep_from
+            with torch.cuda.stream(stream):
+                dst[:, :n].copy_(src[:, keep_from - b.buf_start: keep_from - b.buf_start + n])
+            b.active = 1 - b.active
+            b.buf_start = keep_from
+        off = b.t_end - b.buf_start
+        with torch.cuda.stream(stream):
+            b.buf[b.active][:, off: off + B].copy_(block)
+        b.t_end += B
+
+    def _launch(self, s: _Slot, reqs: List[Request], mem: int):
+        import torch
+        st = s.stream
+        arr = (spd.Beam * len(reqs))()
+        searched = []
+        for r in reqs:
+            b = self.beams[r.beam]
+            b.busy = True
+            if r.ready is not None:
+                st.wait_event(r.ready)
+            self._append(b, r.block, st)
+            r0, r1 = r.region
+            if r1 > r0:
+                searched.append(r)
+            b.r0 = r1
+        for i, r in enumerate(searched):
+            b = self.beams[r.beam]
+            r0, r1 = r.region
+            t0 = max(0, r0 - self.grain)
+            n_out = r1 + self.grain - t0
+            n_in = min(b.t_end, r1 + self.grain + self.l_end - 1) - t0
+            x = b.buf[b.active]
+            a = arr[i]
+            a.x = x.data_ptr() + (t0 - b.buf_start) * 4
+            a.ld, a.n_dm, a.n_in, a.n_out, a.t0 = b.cap, b.n_dm, n_in, n_out, t0
+            a.mean, a.sigma = b.mean.data_ptr(), b.sigma.data_ptr()
+            a.snr = a.width = None
+            a.cand = s.cand[reqs.index(r)].data_ptr()
+            a.cand_cap = self.cand_cap
+            a.cand_count = s.count[reqs.index(r)].data_ptr()
+        if searched:
+            n = len(searched)
+            wsb, tb = ctypes.c_int64(), ctypes.c_int64()
+            spd._check(self.lib.spd_batch_plan(ctypes.byref(self.params), n, arr,
+                                               ctypes.byref(wsb), ctypes.byref(tb)), "spd_batch_plan")
+            if wsb.value > s.ws.numel() or tb.value > s.table_dev.numel():
+                raise RuntimeError("batch slot too small for the admitted windows")
+            spd._check(self.lib.spd_batch_table(ctypes.byref(self.params), n, arr,
+                                                ctypes.c_void_p(s.ws.data_ptr()),
+                                                ctypes.c_void_p(s.table_host.data_ptr()), tb.value),
+                       "spd_batch_table")
+            with torch.cuda.stream(st):
+                s.table_dev[: tb.value].copy_(s.table_host[: tb.value], non_blocking=True)
+            spd._check(self.lib.spd_batch_search(ctypes.byref(self.params), n, arr,
+                                                 ctypes.c_void_p(s.table_dev.data_ptr()),
+                                                 ctypes.c_void_p(s.ws.data_ptr()), s.ws.numel(), 0,
+                                                 ctypes.c_void_p(st.cuda_stream)), "spd_batch_search")
+            with torch.cuda.stream(st):
+                s.count_host.copy_(s.count, non_blocking=True)
+                s.cand_host.copy_(s.cand, non_blocking=True)
+        s.reqs = reqs
+        s.mem = mem
+        s.busy = True
+        self.mem_in_flight += mem
+        s.done.record(st)
+
+    # ------------------------------------------------------------------ reporting
+    def latencies(self) -> np.ndarray:
+        return np.array([r.latency for r in self.results])
+
+
+def offline_region_candidates(x, mean, sigma, cfg: "spd.Config", r_end: int) -> np.ndarray:
+    """Whole-stream candidates with start < r_end (the regions a stream has finished)."""
+    res = spd.search(x, mean, sigma, cfg, cand_cap=1 << 20)
+    c = res.candidates_host()
+    return c[c["start"] < r_end]

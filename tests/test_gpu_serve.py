@@ -1,0 +1,121 @@
+"""GPU tests of the streaming server with continuous batching (paper_1910_08324_amd/serve.py):
+the candidates of every block are exactly the whole-stream candidates of its region, and they
+are the same whether the beam is served alone or mixed with other beams."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    from paper_1910_08324_amd import serve, spd
+    spd.load()
+    return serve
+
+
+def stream(beam, n_dm, sizes, seed=0):
+    """Deterministic blocks of a beam: noise plus a few boxcar pulses, generated on the GPU."""
+    g = torch.Generator(device="cuda")
+    out = []
+    for i, B in enumerate(sizes):
+        g.manual_seed(seed * 1000003 + beam * 1009 + i)
+        x = torch.randn((n_dm, B), generator=g, device="cuda")
+        if i % 3 == 1:
+            x[beam % n_dm, B // 3: B // 3 + 40] += 2.0
+        out.append(x)
+    return out
+
+
+def sizes_for(beam, n_blocks, seed=0):
+    rng = np.random.default_rng(1000 + beam + seed)
+    return [int(v) * 256 for v in rng.integers(4, 33, n_blocks)]      # 1024 .. 8192
+
+
+def run(S, beams, order, **kw):
+    srv = S.StreamServer(method=kw.pop("method", "ig1"), l_end=kw.pop("l_end", 2048),
+                         threshold=4.5, max_block=8192, slots=kw.pop("slots", 3), **kw)
+    for b, blocks in beams.items():
+        srv.open_beam(b, blocks[0].shape[0])
+    for b, i in order:
+        srv.submit(b, beams[b][i])
+        srv.poll()
+    srv.drain()
+    return srv
+
+
+@pytest.mark.parametrize("method", ["ig1", "bd16"])
+def test_stream_regions_equal_whole_stream(S, method):
+    from paper_1910_08324_amd import spd
+    say(f"[serve] whole-stream equality {method}")
+    n_dm = 24
+    sizes = sizes_for(0, 14)
+    blocks = stream(0, n_dm, sizes)
+    srv = run(S, {0: blocks}, [(0, i) for i in range(len(blocks))], method=method)
+    res = sorted(srv.results, key=lambda r: r.index)
+    assert [r.index for r in res] == list(range(len(blocks)))
+    r_end = max(r.region[1] for r in res)
+    assert r_end > 0
+    for a, b in zip(res, res[1:]):
+        assert a.region[1] == b.region[0]                  # regions tile the stream
+    got = np.concatenate([r.candidates for r in res])
+    x = torch.cat(blocks, dim=1).contiguous()
+    cfg = spd.Config(method, 2048, threshold=4.5)
+    ref = S.offline_region_candidates(x, torch.zeros(n_dm, device="cuda"),
+                                      torch.ones(n_dm, device="cuda"), cfg, r_end)
+    key = lambda c: np.lexsort((c["start"], c["dm"], c["level"]))
+    got = got[key(got)]
+    say(f"  regions end {r_end}, candidates {len(got)}")
+    assert len(ref) > 0 and np.array_equal(got, ref)
+
+
+def test_alone_equals_mixed(S):
+    say("[serve] alone vs mixed")
+    n_dm = 16
+    beams = {b: stream(b, n_dm, sizes_for(b, 10), seed=1) for b in range(5)}
+    alone = run(S, {0: beams[0]}, [(0, i) for i in range(10)])
+    rng = np.random.default_rng(4)
+    order = [(b, i) for b in beams for i in range(10)]
+    # interleave the beams' blocks at random, each beam's blocks in order
+    pos = {b: 0 for b in beams}
+    mixed_order = []
+    while len(mixed_order) < len(order):
+        b = int(rng.choice([b for b in beams if pos[b] < 10]))
+        mixed_order.append((b, pos[b]))
+        pos[b] += 1
+    mixed = run(S, beams, mixed_order, slots=2, max_beams_per_batch=3)
+    A = {r.index: r for r in alone.results}
+    M = {r.index: r for r in mixed.results if r.beam == 0}
+    assert sorted(A) == sorted(M) == list(range(10))
+    for i in range(10):
+        assert A[i].region == M[i].region
+        assert np.array_equal(A[i].candidates, M[i].candidates), i
+    batched = max(len(s) for s in [[r for r in mixed.results if r.done == d]
+                                   for d in set(r.done for r in mixed.results)])
+    say(f"  largest batch retired together: {batched}")
+    assert batched >= 2                                   # requests really were batched
+
+
+def test_budget_limits_admission(S):
+    n_dm = 16
+    beams = {b: stream(b, n_dm, [4096] * 4, seed=2) for b in range(3)}
+    srv = S.StreamServer(l_end=2048, threshold=4.5, max_block=8192, slots=3, hbm_budget=1)
+    for b in beams:
+        srv.open_beam(b, n_dm)
+    for i in range(4):
+        for b in beams:
+            srv.submit(b, beams[b][i])
+    srv.poll()
+    # nothing whose window needs memory fits a 1-byte budget; blocks with empty regions pass
+    assert all(r.region[0] == r.region[1] for r in srv.results)
+    assert len(srv.queue) > 0
