@@ -174,6 +174,10 @@ def main():
     ap.add_argument("--batch-dm-scale", type=int, default=8,
                     help="divide the batched run's DM counts (512..4096) by this (1: full size)")
     ap.add_argument("--batch-ws-gb", type=float, default=120.0, help="workspace budget per fused group")
+    ap.add_argument("--serve-blocks", type=int, default=24,
+                    help="blocks per beam of the streaming-server run (0: skip)")
+    ap.add_argument("--serve-speed", type=float, default=20.0,
+                    help="arrival pacing of the served run, in multiples of real time")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -399,6 +403,11 @@ def main():
         torch.cuda.empty_cache()
         batch = batch_section(args, dev)
 
+    served = None
+    if args.serve_blocks > 0:
+        torch.cuda.empty_cache()
+        served = serve_section(args, dev)
+
     prop = None
     if args.proposal_tiles > 0:
         torch.cuda.empty_cache()
@@ -438,6 +447,8 @@ def main():
         out["mean_loss_vs_exhaustive"] = methods[args.method]["mean_loss"]
     if batch is not None:
         out["batch"] = batch
+    if served is not None:
+        out["serving"] = served
     if prop is not None:
         out["proposal"] = prop
     print(json.dumps(out), flush=True)
@@ -518,6 +529,96 @@ def batch_section(args, dev) -> dict:
             "one_by_one_dm_samples_per_s": samples / (single_ms * 1e-3),
             "groups": desc, "tuning_seconds": round(tune_s, 1),
             "shapes": shapes}
+
+
+def serve_section(args, dev) -> dict:
+    """Streaming server: 8 beams x 4096 DMs arriving as 1024..8192-sample blocks (device
+    resident, as from a dedispersion stage), L_end 8192, 64 GB HBM admission budget.  A
+    saturated run (every block queued at once) gives the sustained throughput; a paced run
+    (blocks arrive at `serve_speed` times real time) gives block latencies."""
+    import numpy as np
+    import torch
+    from paper_1910_08324_amd import serve
+
+    n_beams, n_dm, nb = 8, 4096, args.serve_blocks
+    rng = np.random.default_rng(5)
+    sizes = {b: [int(v) * 256 for v in rng.integers(4, 33, nb)] for b in range(n_beams)}
+    g = torch.Generator(device=dev)
+    blocks = {}
+    for b in range(n_beams):
+        blocks[b] = []
+        for i, B in enumerate(sizes[b]):
+            g.manual_seed(b * 100003 + i)
+            blocks[b].append(torch.randn((n_dm, B), generator=g, device=dev))
+    torch.cuda.synchronize()
+    samples = {b: sum(sizes[b]) for b in sizes}
+
+    def make():
+        srv = serve.StreamServer(method=args.method, l_end=8192, threshold=5.0, max_block=8192,
+                                 hbm_budget=64 << 30, slots=3, max_beams_per_batch=n_beams,
+                                 device=dev)
+        for b in range(n_beams):
+            srv.open_beam(b, n_dm)
+        return srv
+
+    # warm-up (allocations, first launches)
+    srv = make()
+    for b in range(n_beams):
+        srv.submit(b, blocks[b][0])
+    srv.drain()
+    del srv
+    # saturated: everything queued at t = 0
+    srv = make()
+    t0 = time.perf_counter()
+    for i in range(nb):
+        for b in range(n_beams):
+            srv.submit(b, blocks[b][i], arrival=t0)
+            srv.poll()
+    srv.drain()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    searched = sum(r.region[1] - r.region[0] for r in srv.results) * n_dm
+    beam_seconds = sum(samples.values()) * T_SAMPLE
+    sat = {"wall_s": round(wall, 4), "beam_seconds": round(beam_seconds, 3),
+           "rtf_beams": round(beam_seconds / wall, 1),
+           "dm_samples_per_s": searched / wall,
+           "batches": len(set(r.done for r in srv.results))}
+    del srv
+    # paced: block i of beam b arrives when its last sample exists, at serve_speed x real time
+    srv = make()
+    events = []
+    for b in range(n_beams):
+        t = 0.0
+        for i, B in enumerate(sizes[b]):
+            t += B * T_SAMPLE / args.serve_speed
+            events.append((t, b, i))
+    events.sort()
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(events) or srv.queue or any(s.busy for s in srv.slots):
+        now = time.perf_counter() - t0
+        while k < len(events) and events[k][0] <= now:
+            ta, b, i = events[k]
+            srv.submit(b, blocks[b][i], arrival=t0 + ta)
+            k += 1
+        if srv.poll() == 0:
+            time.sleep(50e-6)
+    lat = np.array([r.latency for r in srv.results]) * 1e3
+    paced = {"speed_x_realtime": args.serve_speed, "blocks": len(lat),
+             "p50_ms": round(float(np.percentile(lat, 50)), 3),
+             "p99_ms": round(float(np.percentile(lat, 99)), 3),
+             "max_ms": round(float(lat.max()), 3),
+             "batches": len(set(r.done for r in srv.results))}
+    # a region waits for L_end - 1 + 2^K later samples before it can be searched at all
+    inherent = (8192 - 1 + 2 * srv.grain) * T_SAMPLE
+    del srv
+    torch.cuda.empty_cache()
+    log(f"[bench] serving: saturated {sat['rtf_beams']:.0f} beam-seconds per second "
+        f"({sat['dm_samples_per_s']:.3e} DM*samples/s); paced at {args.serve_speed:g}x real time: "
+        f"p50 {paced['p50_ms']} ms, p99 {paced['p99_ms']} ms")
+    return {"beams": n_beams, "n_dm": n_dm, "blocks_per_beam": nb, "block_samples": "1024..8192",
+            "l_end": 8192, "hbm_budget_gb": 64, "method": args.method, "saturated": sat,
+            "paced": paced, "inherent_wait_s": round(inherent, 3)}
 
 
 def proposal_section(args, dev) -> dict:
