@@ -33,7 +33,9 @@ int oracle_threads(void)
 #endif
 }
 
-static void one_slot(const double *P, int64_t s, int32_t n_in, double sigma,
+/* wsig: NULL for the white-noise scaling sqrt(L) sigma, else the row's sigma of every width L
+ * at wsig[L] (a measured standard-deviation table, Section 4.6). */
+static void one_slot(const double *P, int64_t s, int32_t n_in, double sigma, const double *wsig,
                      const int32_t *w, int32_t nw, double *Y, int32_t *W, double *gap)
 {
     double best = -INFINITY, second = -INFINITY;
@@ -41,7 +43,7 @@ static void one_slot(const double *P, int64_t s, int32_t n_in, double sigma,
     for (int32_t j = 0; j < nw; ++j) {
         int64_t L = w[j];
         if (s + L > n_in) continue;                       /* valid-only boundary */
-        double snr = (P[s + L] - P[s]) / (sqrt((double)L) * sigma);
+        double snr = (P[s + L] - P[s]) / (wsig ? wsig[L] : sqrt((double)L) * sigma);
         if (snr > best) {                                 /* ascending widths: ties keep the smaller */
             second = best;
             best = snr;
@@ -64,7 +66,8 @@ static void one_slot(const double *P, int64_t s, int32_t n_in, double sigma,
 void oracle_planes(const float *x, int64_t ld, int32_t n_dm, int32_t n_in, int32_t n_out,
                    const float *mean, const float *sigma, int32_t n_levels,
                    const int32_t *level_k, const int32_t *wptr, const int32_t *widths,
-                   const int64_t *plane_off, double *Y, int32_t *W, double *gap)
+                   const int64_t *plane_off, double *Y, int32_t *W, double *gap,
+                   const double *wsig, int64_t wsig_ld)
 {
 #pragma omp parallel
     {
@@ -80,7 +83,8 @@ void oracle_planes(const float *x, int64_t ld, int32_t n_dm, int32_t n_in, int32
                 int64_t slots = ((int64_t)n_out + stride - 1) / stride;
                 int64_t base = plane_off[i] + (int64_t)d * slots;
                 for (int64_t m = 0; m < slots; ++m)
-                    one_slot(P, m * stride, n_in, sg, widths + wptr[i], wptr[i + 1] - wptr[i],
+                    one_slot(P, m * stride, n_in, sg, wsig ? wsig + (int64_t)d * wsig_ld : NULL,
+                             widths + wptr[i], wptr[i + 1] - wptr[i],
                              Y + base + m, W + base + m, gap + base + m);
             }
         }

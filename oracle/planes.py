@@ -38,7 +38,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
-        lib.oracle_planes.argtypes = [P, i64, i32, i32, i32, P, P, i32, P, P, P, P, P, P, P]
+        lib.oracle_planes.argtypes = [P, i64, i32, i32, i32, P, P, i32, P, P, P, P, P, P, P, P, i64]
         lib.oracle_planes.restype = None
         lib.oracle_points.argtypes = [P, i64, i32, P, P, P, P, P, i64, P, P, P, P, P, P]
         lib.oracle_points.restype = None
@@ -68,8 +68,10 @@ def slots(n_out: int, k: int) -> int:
 
 
 def planes(x: np.ndarray, mean, sigma, levels: Sequence[Level], n_out: int | None = None,
-           n_in: int | None = None) -> List[Dict[str, np.ndarray]]:
-    """Per level: {'k', 'Y' (n_dm, slots) f64, 'W' int32, 'gap' f64}."""
+           n_in: int | None = None, width_sigma=None) -> List[Dict[str, np.ndarray]]:
+    """Per level: {'k', 'Y' (n_dm, slots) f64, 'W' int32, 'gap' f64}.  width_sigma: None for
+    the white-noise scaling, else an array [n_dm][max width + 1] holding each row's standard
+    deviation of the boxcar sum of every width L at [d][L] (Section 4.6)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     n_dm, ld = x.shape
     n_in = ld if n_in is None else int(n_in)
@@ -84,8 +86,14 @@ def planes(x: np.ndarray, mean, sigma, levels: Sequence[Level], n_out: int | Non
     Y = np.empty(total, np.float64)
     W = np.empty(total, np.int32)
     G = np.empty(total, np.float64)
+    ws, ws_ld = None, 0
+    if width_sigma is not None:
+        ws = np.ascontiguousarray(width_sigma, dtype=np.float64)
+        assert ws.shape[0] == n_dm and ws.shape[1] > int(widths.max())
+        ws_ld = ws.shape[1]
     _load().oracle_planes(_ptr(x), ld, n_dm, n_in, n_out, _ptr(mean), _ptr(sigma), len(levels),
-                          _ptr(ks), _ptr(wptr), _ptr(widths), _ptr(off), _ptr(Y), _ptr(W), _ptr(G))
+                          _ptr(ks), _ptr(wptr), _ptr(widths), _ptr(off), _ptr(Y), _ptr(W), _ptr(G),
+                          _ptr(ws) if ws is not None else None, ctypes.c_int64(ws_ld))
     out = []
     for i, k in enumerate(ks):
         a, b = int(off[i]), int(off[i]) + sizes[i]

@@ -77,3 +77,22 @@ def test_rho_interpolation():
     assert msd.rho_of_width(rho, 3) == pytest.approx(1.2 + 0.3 * (math.log2(3) - 1), rel=1e-14)
     assert msd.rho_of_width(rho, 100) == 1.5
     assert msd.sigma_of_width(2.0, [1.0, 1.0, 1.0], 3) == pytest.approx(2.0 * math.sqrt(3))
+
+
+def test_planes_with_width_sigma_table():
+    """A width-sigma table equal to sqrt(L) sigma reproduces the white-noise planes; a table
+    scaled by c divides every SNR by c (the arg-max widths do not move)."""
+    from oracle import planes, widths
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((3, 3000)).astype(np.float32)
+    mu = np.zeros(3, np.float32)
+    sg = np.array([1.0, 1.5, 0.7], np.float32)
+    lv = widths.method_levels("ig1", 300)
+    ref = planes.planes(x, mu, sg, lv)
+    Lmax = 301
+    ws = np.sqrt(np.arange(Lmax))[None, :] * sg.astype(np.float64)[:, None]
+    same = planes.planes(x, mu, sg, lv, width_sigma=ws)
+    half = planes.planes(x, mu, sg, lv, width_sigma=2.0 * ws)
+    for a, b, c in zip(ref, same, half):
+        assert np.array_equal(a["Y"], b["Y"]) and np.array_equal(a["W"], b["W"])
+        assert np.allclose(c["Y"], a["Y"] / 2, rtol=1e-15) and np.array_equal(c["W"], a["W"])
