@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SPD_ABI_VERSION 3
+#define SPD_ABI_VERSION 4
 
 /* Status codes. */
 #define SPD_OK          0
@@ -86,6 +86,13 @@ extern "C" {
  *   step_levels     BoxDIT / IGRID: separation levels computed on chip per kernel launch, 1..6,
  *                   or 0 for the library's choice (4, fewer if a tile's buffers would not fit).
  *                   Results do not depend on it.  Exhaustive: must be 0.
+ *   rho, n_rho      NULL / 0 for the white-noise scaling sigma(L) = sqrt(L) sigma (Section 2.1).
+ *                   Otherwise a DEVICE array [n_dm][n_rho] (the one exception to "host
+ *                   pointers" here; read by the kernels): rho[d][k] = sd of row d decimated to
+ *                   width 2^k over sqrt(2^k) sd_0, as spd_msd writes it, and the search uses
+ *                   sigma(L) = sqrt(L) sigma[d] rho_d(L), rho_d linear in log2 L between adjacent
+ *                   powers of two and held at rho[d][n_rho-1] above (Section 4.6).  1..24 levels.
+ *                   Not supported by the batched search.
  */
 typedef struct {
     int32_t method;
@@ -100,6 +107,8 @@ typedef struct {
     uint32_t flags;
     int32_t segment;
     int32_t step_levels;
+    const float *rho;
+    int32_t n_rho;
 } spd_params;
 
 /* One candidate (24 bytes).  start = t0 + m 2^k is the first sample of the boxcar; the pulse

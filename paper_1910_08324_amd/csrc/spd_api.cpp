@@ -173,7 +173,7 @@ constexpr int kDefaultStepLevels = 4;
 
 // One launch of the cascade kernel: levels k0 .. k0+J-1 over tiles of T units of its input.
 struct StepPlan {
-    int k0 = 0, J = 0, T = 0, tiles = 0, maxu = 8, lds_bytes = 0;
+    int k0 = 0, J = 0, T = 0, tiles = 0, maxu = 8, lds_bytes = 0, lds_sc = 0;
     bool has_out = false;
     int64_t in_len = 0;        // units of the input series per row
     int64_t out_len = 0;       // units handed to the next step per row
@@ -194,6 +194,7 @@ struct Layout {
     int tile_slots[kMaxLevels] = {0};
     int64_t off_scale = 0, off_mask = 0, off_cnt = 0, off_ent = 0, off_surv = 0, off_msk = 0;
     int64_t off_wtot = 0, off_woff = 0, off_Y = -1, off_W = -1;
+    int64_t scale_ld = 0;
 };
 
 // Lay out one step: units each level must form in a tile, LDS buffers, 1/sqrt(L) tables.
@@ -280,6 +281,8 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
 int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in, int32_t n_out,
                 Layout *L) {
     if (n_dm < 1 || n_in < 1 || n_out < 1 || n_out > n_in) return SPD_EINVAL;
+    if (p->rho && (p->n_rho < 1 || p->n_rho > SPD_MAX_LEVELS)) return SPD_EINVAL;
+    if (!p->rho && p->n_rho != 0) return SPD_EINVAL;
     if ((int64_t)n_in > (int64_t)INT32_MAX - (1 << 20)) return SPD_EINVAL;
     std::memset(&L->info, 0, sizeof(L->info));
     spd_plan_info &I = L->info;
@@ -337,6 +340,12 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
             int lds = -1;
             for (;;) {
                 lds = plan_step(s, k0, J, Tj, &st);
+                if (lds >= 0 && p->rho) {
+                    // this row's width scales: kStepMaxLevels x kMaxLevelWidths floats after the buffers
+                    st.lds_sc = st.lds_bytes / 4;
+                    st.lds_bytes += spd::kStepMaxLevels * spd::kMaxLevelWidths * 4;
+                    lds = st.lds_bytes;
+                }
                 if (lds >= 0 && lds <= 60 * 1024) break;
                 if (J > 1) {
                     --J;
@@ -410,8 +419,10 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
     L->slabs_per_wave = ceil_div(L->n_slabs, L->n_waves);
     L->n_waves = (int)ceil_div(L->n_slabs, L->slabs_per_wave);
 
-    // the exhaustive kernel's masked tail group reads up to kExhGroup entries past the tables
-    L->off_scale = take(((int64_t)L->n_scale + spd::kExhGroup) * 4);
+    // the exhaustive kernel's masked tail group reads up to kExhGroup entries past the tables;
+    // with a sigma table every row has its own
+    L->scale_ld = (!lossy && p->rho) ? (int64_t)L->n_scale + spd::kExhGroup : 0;
+    L->off_scale = take(((int64_t)L->n_scale + spd::kExhGroup) * 4 * (L->scale_ld ? n_dm : 1));
     L->off_mask = take(s.dense ? 4 : (ceil_div(s.l_end, 32) + 4) * 4);
     L->off_cnt = take(L->n_slabs * 4);
     L->off_ent = take(L->n_slabs * L->slab_cap * 4);
@@ -518,6 +529,10 @@ void fill_step_shared(const spd_params *params, const Search &s, const StepPlan 
     a->carry = s.method == SPD_BOXDIT;
     a->want_cand = (params->flags & SPD_WRITE_CANDIDATES) != 0;
     a->threshold = params->threshold;
+    a->rho = params->rho;
+    a->ld_rho = params->n_rho;
+    a->n_rho = params->n_rho;
+    a->lds_sc = st.lds_sc;
     for (int j = 0; j <= st.J && j <= spd::kStepMaxLevels; ++j) a->lv[j] = st.lv[j];
     std::memcpy(a->rtab, st.rtab, sizeof(a->rtab));
 }
@@ -590,8 +605,14 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
     uint32_t *evalmask = reinterpret_cast<uint32_t *>(P.ws + L.off_mask);
     {
         spd::ScaleArgs a;
+        std::memset(&a, 0, sizeof(a));
         a.scale = scale;
         a.n = L.n_scale;
+        a.rho = params->rho;
+        a.ld_rho = params->n_rho;
+        a.n_rho = params->n_rho;
+        a.n_rows = n_dm;
+        a.row_ld = L.scale_ld;
         const int err = spd::launch_scales(a, hip_stream);
         if (err) return hip_fail(err);
         if (const int e2 = mark()) return hip_fail(e2);
@@ -615,6 +636,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
     a.Y = P.Y;
     a.W = P.W;
     a.scale = scale;
+    a.scale_ld = L.scale_ld;
     a.evalmask = evalmask;
     a.slab_cnt = slab_cnt;
     a.slab_ent = slab_ent;
@@ -688,7 +710,7 @@ struct BatchPlan {
 
 int batch_plan(const spd_params *params, int32_t n_beams, const spd_beam *beams, BatchPlan *B) {
     if (!params || !beams || n_beams < 1 || n_beams > (1 << 16)) return SPD_EINVAL;
-    if (params->method == SPD_EXHAUSTIVE) return SPD_EINVAL;
+    if (params->method == SPD_EXHAUSTIVE || params->rho) return SPD_EINVAL;
     int st = build_search(params, &B->s);
     if (st != SPD_OK) return st;
     B->L.resize(n_beams);

@@ -68,6 +68,10 @@ struct StepArgs {
     int32_t vec_ok;           // rows of `in` are 16-byte aligned
     int32_t want_cand;
     float threshold;
+    const float *rho;         // per-row sigma-table ratios [n_dm][ld_rho] at widths 2^0.. (or null)
+    int64_t ld_rho;
+    int32_t n_rho;
+    int32_t lds_sc;           // LDS offset (floats) of the per-row width scales (rho != null)
     StepLevel lv[kStepMaxLevels + 1];
     float rtab[kStepMaxLevels][kMaxLevelWidths];   // 1/sqrt(base + U 2^k) at [j][U-1]
 };
@@ -108,7 +112,8 @@ struct ExhArgs {
     const float *sigma;
     float *Y;
     uint16_t *W;
-    const float *scale;       // 1/sqrt(L), L = 1..l_end at index L-1
+    const float *scale;       // 1/sqrt(L) (or 1/sigma-table ratio), L = 1..l_end at index L-1
+    int64_t scale_ld;         // 0: one table for every row; else row d's table at d * scale_ld
     const uint32_t *evalmask; // bit (L-1) set if width L is evaluated (list mode only)
     uint32_t *slab_cnt;
     uint32_t *slab_ent;
@@ -123,6 +128,11 @@ struct ExhArgs {
 struct ScaleArgs {
     float *scale;             // 1/sqrt(L) for L = 1..n at index L-1 (exhaustive search)
     int32_t n;
+    int32_t n_rows;           // rho != null: one table per row, row d at d * row_ld
+    int64_t row_ld;
+    const float *rho;         // [n_rows][ld_rho]: scale = 1 / (sqrt(L) rho_d(L))
+    int64_t ld_rho;
+    int32_t n_rho;
 };
 
 struct MaskArgs {

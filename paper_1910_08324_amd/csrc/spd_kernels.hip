@@ -35,9 +35,28 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
 // every kernel scales a boxcar sum by the correctly rounded 1/sqrt(L) (white-noise scaling,
 // Section 2.1).  The cascade kernel builds its own small table in LDS the same way.
 // ----------------------------------------------------------------------------------------
+// rho_d(L) of a measured standard-deviation table (Section 4.6): linear in log2 L between the
+// values at adjacent powers of two, held at the last level above it.
+__device__ __forceinline__ double rho_of_width(const float *rho_row, int n_rho, double L) {
+    const double a = log2(L);
+    int k = (int)floor(a + 1e-12);
+    if (k >= n_rho - 1) return (double)rho_row[n_rho - 1];
+    if (k < 0) k = 0;
+    const double f = a - k;
+    return (1.0 - f) * (double)rho_row[k] + f * (double)rho_row[k + 1];
+}
+
 __global__ void scales_kernel(const ScaleArgs A) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < A.n) A.scale[t] = (float)(1.0 / sqrt((double)(t + 1)));
+    const int d = blockIdx.y;
+    if (t >= A.n) return;
+    if (!A.rho) {
+        A.scale[t] = (float)(1.0 / sqrt((double)(t + 1)));
+        return;
+    }
+    const double L = (double)(t + 1);
+    const double r = rho_of_width(A.rho + (int64_t)d * A.ld_rho, A.n_rho, L);
+    A.scale[(int64_t)d * A.row_ld + t] = (float)(1.0 / (sqrt(L) * r));
 }
 
 __global__ void evalmask_kernel(const MaskArgs A) {
@@ -234,12 +253,24 @@ struct TabGeom {
 
 // One tile (DM row d, tile `tile`) of a cascade launch.  A holds what every beam of the launch
 // shares (levels, width patterns, tile length); G the beam's buffers and sizes.
-template <bool FIRST, int FAM, class G>
+template <bool FIRST, int FAM, bool RHO, class G>
 __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const int d,
                                           const int tile, float *lds, uint32_t *st_cnt) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int T = A.T;
+    if (RHO) {
+        // this row's 1/sigma(L) relative to 1/(sqrt(L) sigma): scale[j][u-1] = rtab[j][u-1] / rho(L)
+        const float *rr = A.rho + (int64_t)d * A.ld_rho;
+        float *sc = lds + A.lds_sc;
+        for (int i = tid; i < A.J * kMaxLevelWidths; i += kStepThreads) {
+            const int j = i / kMaxLevelWidths, u = i - j * kMaxLevelWidths + 1;
+            if (u <= A.lv[j].umax) {
+                const double L = (double)A.lv[j].base + ldexp((double)u, A.lv[j].k);
+                sc[i] = (float)((double)A.rtab[j][u - 1] / rho_of_width(rr, A.n_rho, L));
+            }
+        }
+    }
     const int64_t u0 = (int64_t)tile * T;
     if (tid < kStepMaxLevels) st_cnt[tid] = 0;
 
@@ -315,7 +346,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         const int umax = L.umax;
         const int base = L.base;
         const int pat = L.pattern;
-        const float *rt = A.rtab[j];
+        const float *rt = RHO ? lds + A.lds_sc + j * kMaxLevelWidths : A.rtab[j];
         float *rowY = V.Y() + V.plane_off(j) + (int64_t)d * V.pitch(j);
         uint16_t *rowW = V.W() + V.plane_off(j) + (int64_t)d * V.pitch(j);
         // a group is "fast" when the widest boxcar of its last slot ends inside the data
@@ -453,14 +484,14 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
 
 
 // One launch for one beam: work-group = (DM row, tile).
-template <bool FIRST, int FAM>
+template <bool FIRST, int FAM, bool RHO>
 __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(const StepArgs A) {
     extern __shared__ float lds[];
     __shared__ uint32_t st_cnt[kStepMaxLevels];
     const int d = blockIdx.x / A.n_tiles;
     const int tile = blockIdx.x - d * A.n_tiles;
     if (d >= A.n_dm) return;
-    step_tile<FIRST, FAM>(A, ArgGeom{A}, d, tile, lds, st_cnt);
+    step_tile<FIRST, FAM, RHO>(A, ArgGeom{A}, d, tile, lds, st_cnt);
 }
 
 // One launch for many beams (same levels and tile length, any sizes): a persistent grid walks
@@ -480,7 +511,7 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel_bat
         const int d = (int)(local / V.n_tiles());
         const int tile = (int)(local - (int64_t)d * V.n_tiles());
         if (item != (int64_t)blockIdx.x) lds_barrier();   // the previous item is done with LDS
-        step_tile<FIRST, FAM>(B.s, V, d, tile, lds, st_cnt);
+        step_tile<FIRST, FAM, false>(B.s, V, d, tile, lds, st_cnt);
     }
 }
 
@@ -544,6 +575,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
     if (d >= A.n_dm) return;
     const int s0 = g * kExhSlots;
     const float *xr = A.x + (int64_t)d * A.ld;
+    const float *srow = A.scale + (int64_t)d * A.scale_ld;     // this row's 1/sigma(L) factors
     const float mu = A.mean[d];
     const float inv = 1.0f / A.sigma[d];
     const int Lw = A.l_end;
@@ -605,9 +637,9 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
             }
             const int jb4 = lane + ((L0 - 1) >> 2);
             if (fast)
-                exh_group<false, DENSE>(ring4, jb4, L0, A.scale, A.evalmask, Lw, room, X, gm);
+                exh_group<false, DENSE>(ring4, jb4, L0, srow, A.evalmask, Lw, room, X, gm);
             else
-                exh_group<true, DENSE>(ring4, jb4, L0, A.scale, A.evalmask, Lw, room, X, gm);
+                exh_group<true, DENSE>(ring4, jb4, L0, srow, A.evalmask, Lw, room, X, gm);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 if (gm[v] > best[v]) {
@@ -637,7 +669,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
             const int L = Lb + t;
             if (L > Lw) break;
             Xr += load_z(xr, sv + L - 1, n_in, mu, inv);
-            float snr = Xr * A.scale[L - 1];
+            float snr = Xr * srow[L - 1];
             bool ok = L <= room[v];
             if (!DENSE) ok = ok && ((A.evalmask[(L - 1) >> 5] >> ((L - 1) & 31)) & 1u);
             if (ok && snr > bm) {
@@ -913,7 +945,8 @@ __global__ __launch_bounds__(256) void peak_scatter_kernel(const PeakArgs A) {
 // ----------------------------------------------------------------------------------------
 int launch_scales(const ScaleArgs &a, void *stream) {
     if (a.n <= 0) return 0;
-    hipLaunchKernelGGL(scales_kernel, dim3((a.n + 255) / 256), dim3(256), 0, (hipStream_t)stream, a);
+    const unsigned rows = a.rho ? (unsigned)a.n_rows : 1u;
+    hipLaunchKernelGGL(scales_kernel, dim3((a.n + 255) / 256, rows), dim3(256), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
@@ -926,7 +959,10 @@ int launch_evalmask(const MaskArgs &a, void *stream) {
 template <bool FIRST, int FAM>
 static int launch_one(const StepArgs &a, int lds_bytes, hipStream_t st) {
     const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_tiles));
-    hipLaunchKernelGGL((step_kernel<FIRST, FAM>), grid, dim3(kStepThreads), lds_bytes, st, a);
+    if (a.rho)
+        hipLaunchKernelGGL((step_kernel<FIRST, FAM, true>), grid, dim3(kStepThreads), lds_bytes, st, a);
+    else
+        hipLaunchKernelGGL((step_kernel<FIRST, FAM, false>), grid, dim3(kStepThreads), lds_bytes, st, a);
     return (int)hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ EXHAUSTIVE, BOXDIT, IGRID = 0, 1, 2
 WRITE_PLANES, WRITE_CANDIDATES = 1, 2
 MAX_LEVELS = 24
 MAX_LAUNCHES = 26
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class Params(ctypes.Structure):
@@ -38,6 +38,8 @@ class Params(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("segment", ctypes.c_int32),
         ("step_levels", ctypes.c_int32),
+        ("rho", ctypes.c_void_p),
+        ("n_rho", ctypes.c_int32),
     ]
 
 
@@ -136,6 +138,7 @@ class Config:
     igrid_layers: int = 0
     segment: int = 0
     step_levels: int = 0
+    rho: object = None            # device float [n_dm][n_rho] sigma-table ratios (spd_msd), or None
 
     def params(self) -> Tuple[Params, list]:
         keep = []
@@ -146,6 +149,11 @@ class Config:
         p.flags = (WRITE_PLANES if self.planes else 0) | (WRITE_CANDIDATES if self.candidates else 0)
         p.segment = int(self.segment)
         p.step_levels = int(self.step_levels)
+        if self.rho is not None:
+            if self.rho.dim() != 2 or not self.rho.is_contiguous():
+                raise ValueError("rho must be a contiguous [n_dm][n_rho] device tensor")
+            p.rho = self.rho.data_ptr()
+            p.n_rho = int(self.rho.shape[1])
         if m in ("exh", "exhaustive"):
             p.method = EXHAUSTIVE
             if self.widths is not None:

@@ -24,8 +24,9 @@ def tol_of(y):
     return TOL * np.maximum(1.0, np.abs(np.where(np.isfinite(y), y, 0.0)))
 
 
-def check_values(Yg, Wg, Yr, Wr, Gr, x, mu, sg, rows, starts, n_in, what=""):
-    """Element-wise SNR / width check of flat arrays.  rows/starts locate each element."""
+def check_values(Yg, Wg, Yr, Wr, Gr, x, mu, sg, rows, starts, n_in, what="", width_sigma=None):
+    """Element-wise SNR / width check of flat arrays.  rows/starts locate each element.
+    width_sigma: the per-row table of boxcar standard deviations the search used, if any."""
     Yg = np.asarray(Yg, np.float64)
     Yr = np.asarray(Yr, np.float64)
     Wg = np.asarray(Wg, np.int64)
@@ -48,14 +49,17 @@ def check_values(Yg, Wg, Yr, Wr, Gr, x, mu, sg, rows, starts, n_in, what=""):
     assert len(bad) == 0, f"{what}: width differs at {bad[:5]} gpu={Wg[bad[:5]]} ref={Wr[bad[:5]]}"
     diff = np.nonzero(tie & (Wg != Wr))[0]
     if len(diff):
-        v = oplanes.snr(x, mu, sg, np.asarray(rows)[diff], np.asarray(starts)[diff], Wg[diff],
-                        n_in=n_in)
+        rr = np.asarray(rows)[diff]
+        v = oplanes.snr(x, mu, sg, rr, np.asarray(starts)[diff], Wg[diff], n_in=n_in)
+        if width_sigma is not None:
+            sgv = np.broadcast_to(np.asarray(sg, np.float64), (len(width_sigma),))[rr]
+            v = v * np.sqrt(Wg[diff].astype(np.float64)) * sgv / width_sigma[rr, Wg[diff]]
         ok = np.abs(v - Yr[diff]) <= 2 * tol_of(Yr[diff])
         assert ok.all(), f"{what}: near-tie width not within tolerance at {diff[~ok][:5]}"
     return int(fin.sum()), int(len(diff))
 
 
-def check_planes(gpu_planes, ref_planes, x, mu, sg, n_in, what=""):
+def check_planes(gpu_planes, ref_planes, x, mu, sg, n_in, what="", width_sigma=None):
     assert len(gpu_planes) == len(ref_planes)
     stats = []
     for i, (g, r) in enumerate(zip(gpu_planes, ref_planes)):
@@ -66,7 +70,7 @@ def check_planes(gpu_planes, ref_planes, x, mu, sg, n_in, what=""):
         starts = np.tile(np.arange(slots, dtype=np.int64) << r["k"], n_dm)
         stats.append(check_values(g["Y"].ravel(), g["W"].ravel(), r["Y"].ravel(), r["W"].ravel(),
                                   r["gap"].ravel(), x, mu, sg, rows, starts, n_in,
-                                  what=f"{what} level {i}"))
+                                  what=f"{what} level {i}", width_sigma=width_sigma))
     return stats
 
 

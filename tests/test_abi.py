@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib):
                           "spd_prop_adam", "spd_tile_max", "spd_prop_labels"}
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.spd_abi_version() == spd.ABI_VERSION == 3
+    assert lib.spd_abi_version() == spd.ABI_VERSION == 4
 
 
 CASES = [("exh", 1), ("exh", 256), ("exh", 8192), ("dit", 8192)] + \
