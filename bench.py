@@ -77,7 +77,7 @@ def launch_kernel_name(method: str, info, i: int) -> str:
     if method == "exh":
         return "spd::exh_kernel<true>" if info.launch_first_level[i] >= 0 else "spd::scales_kernel"
     first = "true" if info.launch_first_level[i] == 0 else "false"
-    return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}>"
+    return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}, false>"
 
 
 def launch_valu_ops(method: str, cfg, info, i: int, n_dm: int, n_in: int) -> float:
@@ -126,7 +126,7 @@ def dominant_entry(method: str, cfg, run, w, reps: int, lms=None) -> dict:
             "bound": "hbm" if hf >= vf else "alu"}
 
 
-def read_traffic(method: str, kernel: str):
+def read_traffic(method: str, kernel: str, shape=None):
     """HBM bytes per launch of `kernel` from the committed counter summary, if it was taken on
     the current kernel source for this method; else None."""
     if not os.path.exists(PMC_FILE):
@@ -140,6 +140,9 @@ def read_traffic(method: str, kernel: str):
     if vals.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     if vals.get("method") != method or vals.get("kernel") != kernel:
+        return None
+    if (shape is not None and
+            (vals.get("segment") != str(shape[0]) or vals.get("step_levels") != str(shape[1]))):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -164,6 +167,8 @@ def main():
     ap.add_argument("--segment", type=int, default=0, help="tile length override (0: library's)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the library's default launch shape instead of the autotuner's")
+    ap.add_argument("--step-levels", type=int, default=0,
+                    help="levels per cascade launch with --segment (0: library's)")
     ap.add_argument("--profile-probe", action="store_true")
     ap.add_argument("--proposal-tiles", type=int, default=65536,
                     help="tiles of 64 x 4096 to train the learned proposal on (0: skip)")
@@ -210,7 +215,9 @@ def main():
     def config_for(method):
         """The method's search config with the autotuner's launch shape for this beam shape."""
         if tuner is None or method == "exh":
-            return spd.Config(method, w.l_end, threshold=w.threshold, segment=args.segment), None
+            seg, lev = (args.segment, args.step_levels) if method != "exh" else (0, 0)
+            return spd.Config(method, w.l_end, threshold=w.threshold, segment=seg,
+                              step_levels=lev), None
         t0 = time.time()
         c = tuner.choose(method, w.l_end, w.n)
         log(f"[bench] tuned {method}: segment {c.segment}, levels per launch {c.step_levels} "
@@ -241,6 +248,8 @@ def main():
                      "algorithmic_bytes": launch_bytes(info, i, w.n_dm)}
                     for i in range(info.n_launches)]
         print(json.dumps({"probe": "ok", "method": args.method, "search_launches": 4,
+                          "segment": int(info.segment),
+                          "step_levels": max(int(info.launch_levels[i]) for i in range(info.n_launches)),
                           "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes,
                           "copies": [{"op": "mul", "bytes": copy_bytes},
                                      {"op": "mul_strided", "bytes": strided_bytes},
@@ -286,7 +295,9 @@ def main():
         achieved, peak, unit = dom_main["valu_tops"], round(VALU_PEAK_TOPS, 2), "TFLOP/s"
     roofline = {"bound": dom_main["bound"], "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4),
-                "traffic": read_traffic(args.method, dom_main["kernel"]),
+                "traffic": read_traffic(args.method, dom_main["kernel"],
+                                        (info.segment, max(int(info.launch_levels[i])
+                                                           for i in range(info.n_launches)))),
                 "kernel": dom_main["kernel"],
                 "levels": [int(info.launch_first_level[dom]),
                            int(info.launch_first_level[dom] + info.launch_levels[dom] - 1)],
