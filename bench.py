@@ -210,7 +210,7 @@ def main():
     tuner = None
     if not args.no_tune and args.segment == 0:
         from paper_1910_08324_amd import autotune
-        tuner = autotune.Tuner(rows=w.n_dm, reps=2)
+        tuner = autotune.Tuner(rows=w.n_dm, reps=3)
 
     def config_for(method):
         """The method's search config with the autotuner's launch shape for this beam shape."""

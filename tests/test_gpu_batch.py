@@ -128,4 +128,4 @@ def test_autotuner_groups_and_matches(spd):
             same_result(b.results[k], single(spd, beams[i], ref_cfg), ref_cfg, i)
     c = tuner.choose("ig1", 1000, 70000)
     assert c.segment in autotune.SEGMENTS and c.step_levels in autotune.DEPTHS
-    assert c.ms == min(m[2] for m in c.measured)
+    assert c.ms <= min(m[2] for m in c.measured) * (1 + tuner.tolerance)
