@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E peak
 # FP32 vector peak 157.3 TFLOP/s counts an FMA as 2 operations: 256 FLOP per clock per CU on
 # 256 CUs at 2.4 GHz, i.e. 128 single-operation lanes per clock per CU.
 VALU_PEAK_TOPS = 128 * 256 * 2.4e9 / 1e12
-KERNEL_SRC = os.path.join(ROOT, "paper_1910_08324_amd", "csrc", "spd_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1910_08324_amd", "csrc", f)
+              for f in ("spd_kernels.hip", "spd_internal.h", "spd_api.cpp")]
 PMC_FILE = os.path.join(ROOT, "profiles", "lossy_kernel_ska_beam_counters.txt")
 
 
@@ -47,8 +48,13 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the search's kernel, constant and planner sources (a profile is only valid for
+    the code it was taken on)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(info, n_dm: int, n_in: int) -> int:

@@ -563,6 +563,114 @@ __global__ void labels_kernel(const float *e, const float *l, int32_t n, float t
 }
 
 // ---------------------------------------------------------------------------------------
+// Fused inference: one work-group per row runs the three convolutions with the activations in
+// LDS (features 4.2 KB, two activation buffers of 16.8 KB), then the read-out; only the
+// features come from HBM.  Each row leaves its read-out maximum and sum of exp(s - max); a
+// second kernel combines a tile's 64 rows into the logit.  The MFMA sequence is the unfused
+// kernels' one, so the activations are bitwise the same.
+// ---------------------------------------------------------------------------------------
+struct InferArgs {
+    const uint16_t *feat;
+    WB wb;
+    const float *params;
+    float *row_max;            // [rows]
+    float *row_sum;            // [rows]
+    int32_t rows;
+};
+
+// one layer of a row held in LDS: out = relu(W in + b), 2 tiles of 32 positions per wave
+template <int CI>
+__device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, const float *bias,
+                                         uint16_t *out, int wave, int l) {
+    constexpr int KS = (TAPS * CI + 15) / 16;
+    constexpr int KWC = KS * 16;
+    const int h = l >> 5;
+    const int n = l & 31;
+    bf16x8 wa[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) wa[s] = load8(w + n * KWC + 16 * s + 8 * h);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int p0 = wave * 64 + half * 32;
+        f32x16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const bf16x8 b = load8(in + (p0 + n) * CI + 16 * s + 8 * h);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[s], b, acc, 0, 0, 0);
+        }
+        uint16_t *o = out + (p0 + n + 2) * CH;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            uint16_t hv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int co = 8 * g + 4 * h + j;
+                hv[j] = to_bf16(fmaxf(acc[4 * g + j] + bias[co], 0.0f));
+            }
+            *reinterpret_cast<uint2 *>(o + 8 * g + 4 * h) =
+                make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
+                           (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void infer_kernel(const InferArgs A) {
+    __shared__ __attribute__((aligned(16))) uint16_t f[RP * FCH];
+    __shared__ __attribute__((aligned(16))) uint16_t a[RP * CH];
+    __shared__ __attribute__((aligned(16))) uint16_t b[RP * CH];
+    __shared__ float red[8];
+    const int r = blockIdx.x;
+    if (r >= A.rows) return;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int l = tid & 63;
+    const uint16_t *fr = A.feat + (int64_t)r * RP * FCH;
+    for (int i = tid; i < RP * FCH / 8; i += 256)
+        reinterpret_cast<uint4 *>(f)[i] = reinterpret_cast<const uint4 *>(fr)[i];
+    // zero pads of the activation buffers (positions 0, 1, 258 .. 261)
+    for (int i = tid; i < 6 * CH / 8; i += 256) {
+        const int pos = i / (CH / 8), part = i - pos * (CH / 8);
+        const int pp = pos < 2 ? pos : POS + pos;
+        reinterpret_cast<uint4 *>(a)[pp * (CH / 8) + part] = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4 *>(b)[pp * (CH / 8) + part] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+    conv_lds<FCH>(f, A.wb.w1, A.params + SPD_PROP_OFF_B1, a, wave, l);
+    __syncthreads();
+    conv_lds<CH>(a, A.wb.w2, A.params + SPD_PROP_OFF_B2, b, wave, l);
+    __syncthreads();
+    conv_lds<CH>(b, A.wb.w3, A.params + SPD_PROP_OFF_B3, a, wave, l);
+    __syncthreads();
+    // read-out of position tid, then the row's max and sum of exp(s - max)
+    float act[CH];
+    load_act(a + (tid + 2) * CH, act);
+    const float *wh = A.params + SPD_PROP_OFF_WH;
+    float sv = 0.0f;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) sv += wh[c] * act[c];
+    sv += A.params[SPD_PROP_OFF_BH];
+    const float mx = block_max(sv, red);
+    const float se = block_sum(expf(sv - mx), red + 4);
+    if (tid == 0) {
+        A.row_max[r] = mx;
+        A.row_sum[r] = se;
+    }
+}
+
+__global__ void infer_combine_kernel(const float *row_max, const float *row_sum, int32_t n_tiles,
+                                     float *logits) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    float M = -__builtin_huge_valf();
+    for (int j = 0; j < ROWS; ++j) M = fmaxf(M, row_max[t * ROWS + j]);
+    float Z = 0.0f;
+    for (int j = 0; j < ROWS; ++j) Z += row_sum[t * ROWS + j] * expf(row_max[t * ROWS + j] - M);
+    logits[t] = M + logf(Z) - 9.70406052783923f;
+}
+
+// ---------------------------------------------------------------------------------------
 // Workspace layout for n_tiles tiles.
 // ---------------------------------------------------------------------------------------
 struct Layout {
@@ -722,9 +830,22 @@ int spd_prop_forward(const float *params, const uint16_t *feat, int32_t n_tiles,
     const int st = check_ws(n_tiles, workspace, workspace_bytes, &L);
     if (st != SPD_OK) return st;
     if (!params || !feat || !logits) return SPD_EINVAL;
+    if ((uintptr_t)feat & 15) return SPD_EALIGN;
     const Bufs B = bufs(L, workspace);
-    return run_forward(params, feat, n_tiles, nullptr, logits, L, B,
-                       static_cast<hipStream_t>(hip_stream));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int rows = n_tiles * ROWS;
+    SPDP_LAUNCH(prep_weights_kernel, dim3((CH * KW + 255) / 256), dim3(256), 0, s, params, B.wb);
+    InferArgs a;
+    a.feat = feat;
+    a.wb = B.wb;
+    a.params = params;
+    a.row_max = B.s;
+    a.row_sum = B.s + rows;
+    a.rows = rows;
+    SPDP_LAUNCH(infer_kernel, dim3(rows), dim3(256), 0, s, a);
+    SPDP_LAUNCH(infer_combine_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, s, a.row_max,
+                a.row_sum, n_tiles, logits);
+    return SPD_OK;
 }
 
 int spd_prop_backward(const float *params, const uint16_t *feat, const float *labels,

@@ -16,7 +16,7 @@ constexpr int kGroup = 4;             // consecutive slots evaluated together by
 constexpr int kExhSlots = 256;        // output slots per exhaustive work item (64 lanes x 4)
 constexpr int kExhBlock = 512;        // widths per LDS window refill in the exhaustive kernel
 constexpr int kExhGroup = 64;         // widths per max-only group (argmax recovered afterwards)
-constexpr int kSlabCap = 32;          // pre-candidates kept per (level, row, tile)
+constexpr int kSlabCap = 64;          // pre-candidates kept per (level, row, tile): one per lane
 constexpr int kExhSlabCap = 16;       // pre-candidates kept per exhaustive work item
 constexpr int kPeakWaves = 8192;      // waves of the peak-finder passes
 

@@ -106,6 +106,19 @@ def test_forward_matches_oracle(P):
     assert np.allclose(lg, ref, rtol=1e-4, atol=1e-4)
 
 
+def test_fused_inference_matches_training_forward(P):
+    """spd_prop_forward keeps a row's three layers in LDS; its logits equal those of the
+    training forward pass (activations through HBM) up to the order of the final sums."""
+    tiles = 5
+    _, feat = make_batch(P, tiles, seed=41)
+    net = oracle_net(41)
+    N = P.Network(packed(P, net), max_tiles=tiles)
+    lg_fused = N.forward(feat, tiles).cpu().numpy()
+    lg_train = torch.empty(tiles, dtype=torch.float32, device="cuda")
+    N.backward(feat, torch.zeros(tiles, device="cuda"), tiles, logits=lg_train)
+    assert np.allclose(lg_fused, lg_train.cpu().numpy(), rtol=1e-5, atol=1e-5)
+
+
 @pytest.mark.parametrize("seed", [21, 22])
 def test_backward_matches_oracle(P, seed):
     say(f"[proposal] backward seed {seed}")
