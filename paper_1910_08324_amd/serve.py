@@ -15,9 +15,11 @@ exactly the whole-stream candidates there.  Regions start at multiples of 2^K (t
 boxcar spacing), as spd_search requires of t0.
 
 Continuous batching: requests (one per arriving block) wait in arrival order.  Whenever a
-batch slot is free, every waiting request whose beam has no search in flight, and whose memory
-fits the HBM budget beside what is already in flight, is admitted; the admitted windows run as
-ONE fused multi-beam search (spd_batch_search) on that slot's stream.  Several slots are in
+batch slot is free, every beam with waiting blocks and no search in flight is admitted, with up
+to `coalesce` of its queued blocks searched as one window, as long as the windows' memory fits
+the HBM budget beside what is already in flight; the admitted windows run as ONE fused
+multi-beam search (spd_batch_search) on that slot's stream, and each block gets the candidates
+of its own region.  Several slots are in
 flight at once on separate streams, so requests that arrive while others run are admitted as
 slots and memory free up, and their work overlaps on the device.  A block's result depends only
 on its beam's stream, never on what it was batched with.
@@ -93,7 +95,7 @@ class _Slot:
         self.cand_host = torch.empty(tuple(self.cand.shape), dtype=torch.uint8, pin_memory=True)
         self.count_host = torch.empty(max_reqs, dtype=torch.int64, pin_memory=True)
         self.done = torch.cuda.Event()
-        self.reqs: List[Request] = []
+        self.groups: List[List[Request]] = []
         self.busy = False
         self.mem = 0
 
@@ -104,7 +106,7 @@ class StreamServer:
     def __init__(self, method: str = "ig1", l_end: int = 8192, threshold: float = 5.0,
                  max_block: int = 8192, hbm_budget: int = 64 << 30, slots: int = 3,
                  max_beams_per_batch: int = 16, cand_cap: int = 1 << 15, segment: int = 0,
-                 step_levels: int = 0, device="cuda"):
+                 step_levels: int = 0, coalesce: int = 4, device="cuda"):
         import torch
         self.device = torch.device(device)
         self.cfg = spd.Config(method, l_end, threshold=threshold, planes=False, candidates=True,
@@ -115,9 +117,11 @@ class StreamServer:
         self.grain = 1 << int(info.top_level)
         self.l_end = int(l_end)
         self.max_block = int(max_block)
-        # a window spans one grain before the region, the region (at most a block plus the
-        # grain of samples left over) and the look-ahead the last slots' boxcars need
-        self.cap = -(-(self.max_block + self.l_end + 4 * self.grain) // 64) * 64
+        # a beam's queued blocks (up to `coalesce` of them) are searched as one window: a window
+        # spans one grain before the region, the region (at most those blocks plus the grain of
+        # samples left over) and the look-ahead the last slots' boxcars need
+        self.coalesce = max(1, int(coalesce))
+        self.cap = -(-(self.coalesce * self.max_block + self.l_end + 4 * self.grain) // 64) * 64
         self.budget = int(hbm_budget)
         self.max_reqs = int(max_beams_per_batch)
         self.cand_cap = int(cand_cap)
@@ -164,20 +168,6 @@ class StreamServer:
         self.queue.append(r)
         return r
 
-    def _region(self, b: _Beam, t_end: int) -> Tuple[int, int]:
-        g = self.grain
-        r1 = ((t_end - self.l_end + 1 - g) // g) * g
-        return b.r0, max(b.r0, r1)
-
-    def _mem_of(self, b: _Beam, region) -> int:
-        r0, r1 = region
-        if r1 <= r0:
-            return 0
-        t0 = max(0, r0 - self.grain)
-        n_out = r1 + self.grain - t0
-        n_in = min(b.t_end, r1 + self.grain + self.l_end - 1) - t0
-        return self._window_plan(b.n_dm, n_in, n_out)
-
     # ------------------------------------------------------------------ engine
     def poll(self) -> int:
         """Retire finished batches and admit waiting requests; returns the number retired."""
@@ -197,55 +187,69 @@ class StreamServer:
     def _retire(self, s: _Slot):
         now = time.perf_counter()
         counts = s.count_host.numpy()
-        for i, r in enumerate(s.reqs):
-            b = self.beams[r.beam]
+        for i, grp in enumerate(s.groups):
+            b = self.beams[grp[0].beam]
             b.busy = False
-            total = int(counts[i]) if r.region[1] > r.region[0] else 0
+            r0, r1 = grp[0].region[0], grp[-1].region[1]
+            total = int(counts[i]) if r1 > r0 else 0
             if total > self.cand_cap:
-                raise RuntimeError(f"beam {r.beam} block {r.index}: {total} candidates exceed "
-                                   f"the capacity {self.cand_cap}")
+                raise RuntimeError(f"beam {grp[0].beam} blocks {grp[0].index}..{grp[-1].index}: "
+                                   f"{total} candidates exceed the capacity {self.cand_cap}")
             c = s.cand_host[i, : total * spd.CANDIDATE_DTYPE.itemsize].numpy().view(spd.CANDIDATE_DTYPE)
-            keep = (c["start"] >= r.region[0]) & (c["start"] < r.region[1])
-            self.results.append(Result(r.beam, r.index, r.region, c[keep].copy(), r.arrival, now, total))
+            for r in grp:
+                keep = (c["start"] >= r.region[0]) & (c["start"] < r.region[1])
+                self.results.append(Result(r.beam, r.index, r.region, c[keep].copy(), r.arrival,
+                                           now, total))
         self.mem_in_flight -= s.mem
-        s.reqs, s.busy, s.mem = [], False, 0
+        s.groups, s.busy, s.mem = [], False, 0
 
     def _admit(self):
-        import torch
         while self.queue:
             slot = next((s for s in self.slots if not s.busy), None)
             if slot is None:
                 return
-            picked: List[Request] = []
+            groups: List[List[Request]] = []
             taken = set()
             mem = 0
-            for r in list(self.queue):
-                if len(picked) >= self.max_reqs:
+            queued = list(self.queue)
+            for qi, r in enumerate(queued):
+                if len(groups) >= self.max_reqs:
                     break
                 b = self.beams[r.beam]
                 if b.busy or r.beam in taken:
                     taken.add(r.beam)            # keep each beam's blocks in order
                     continue
-                region = self._region(b, b.t_end + r.block.shape[1])
-                need = self._mem_of_after(b, r, region)
+                taken.add(r.beam)
+                # this beam's queued blocks, in order, searched as one window
+                grp = [r] + [q for q in queued[qi + 1:] if q.beam == r.beam][: self.coalesce - 1]
+                t, r0 = b.t_end, b.r0
+                for q in grp:
+                    t += q.block.shape[1]
+                    q.region = (r0, max(r0, self._region_end(t)))
+                    r0 = q.region[1]
+                need = self._mem_of_window(b, grp[0].region[0], r0, t)
                 if self.mem_in_flight + mem + need > self.budget:
                     break                        # first come, first served within the budget
-                r.region, r.mem = region, need
-                picked.append(r)
-                taken.add(r.beam)
+                groups.append(grp)
                 mem += need
-            if not picked:
+            if not groups:
                 return
-            for r in picked:
-                self.queue.remove(r)
-            self._launch(slot, picked, mem)
+            for grp in groups:
+                for q in grp:
+                    self.queue.remove(q)
+            self._launch(slot, groups, mem)
 
-    def _mem_of_after(self, b: _Beam, r: Request, region) -> int:
-        saved = b.t_end
-        b.t_end = saved + r.block.shape[1]
-        m = self._mem_of(b, region)
-        b.t_end = saved
-        return m
+    def _region_end(self, t_end: int) -> int:
+        g = self.grain
+        return ((t_end - self.l_end + 1 - g) // g) * g
+
+    def _mem_of_window(self, b: _Beam, r0: int, r1: int, t_end: int) -> int:
+        if r1 <= r0:
+            return 0
+        t0 = max(0, r0 - self.grain)
+        n_out = r1 + self.grain - t0
+        n_in = min(t_end, r1 + self.grain + self.l_end - 1) - t0
+        return self._window_plan(b.n_dm, n_in, n_out)
 
     def _append(self, b: _Beam, block, stream):
         """Copy a block after the beam's samples, first moving the samples the next window still
@@ -265,38 +269,36 @@ class StreamServer:
             b.buf[b.active][:, off: off + B].copy_(block)
         b.t_end += B
 
-    def _launch(self, s: _Slot, reqs: List[Request], mem: int):
+    def _launch(self, s: _Slot, groups: List[List[Request]], mem: int):
         import torch
         st = s.stream
-        arr = (spd.Beam * len(reqs))()
-        searched = []
-        for r in reqs:
-            b = self.beams[r.beam]
+        arr = (spd.Beam * len(groups))()
+        n = 0
+        for gi, grp in enumerate(groups):
+            b = self.beams[grp[0].beam]
             b.busy = True
-            if r.ready is not None:
-                st.wait_event(r.ready)
-            self._append(b, r.block, st)
-            r0, r1 = r.region
-            if r1 > r0:
-                searched.append(r)
+            for r in grp:
+                if r.ready is not None:
+                    st.wait_event(r.ready)
+                self._append(b, r.block, st)
+            r0, r1 = grp[0].region[0], grp[-1].region[1]
             b.r0 = r1
-        for i, r in enumerate(searched):
-            b = self.beams[r.beam]
-            r0, r1 = r.region
+            if r1 <= r0:
+                continue
             t0 = max(0, r0 - self.grain)
             n_out = r1 + self.grain - t0
             n_in = min(b.t_end, r1 + self.grain + self.l_end - 1) - t0
             x = b.buf[b.active]
-            a = arr[i]
+            a = arr[n]
+            n += 1
             a.x = x.data_ptr() + (t0 - b.buf_start) * 4
             a.ld, a.n_dm, a.n_in, a.n_out, a.t0 = b.cap, b.n_dm, n_in, n_out, t0
             a.mean, a.sigma = b.mean.data_ptr(), b.sigma.data_ptr()
             a.snr = a.width = None
-            a.cand = s.cand[reqs.index(r)].data_ptr()
+            a.cand = s.cand[gi].data_ptr()
             a.cand_cap = self.cand_cap
-            a.cand_count = s.count[reqs.index(r)].data_ptr()
-        if searched:
-            n = len(searched)
+            a.cand_count = s.count[gi].data_ptr()
+        if n:
             wsb, tb = ctypes.c_int64(), ctypes.c_int64()
             spd._check(self.lib.spd_batch_plan(ctypes.byref(self.params), n, arr,
                                                ctypes.byref(wsb), ctypes.byref(tb)), "spd_batch_plan")
@@ -315,7 +317,7 @@ class StreamServer:
             with torch.cuda.stream(st):
                 s.count_host.copy_(s.count, non_blocking=True)
                 s.cand_host.copy_(s.cand, non_blocking=True)
-        s.reqs = reqs
+        s.groups = groups
         s.mem = mem
         s.busy = True
         self.mem_in_flight += mem
