@@ -176,6 +176,10 @@ def main():
     ap.add_argument("--step-levels", type=int, default=0,
                     help="levels per cascade launch with --segment (0: library's)")
     ap.add_argument("--profile-probe", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="the paper's performance shapes instead of the standard line: DM-count, "
+                         "length and L_end sweeps for IG(1) and BD-16, and the small exhaustive "
+                         "workload (64 x 65536, widths 1..256)")
     ap.add_argument("--proposal-tiles", type=int, default=65536,
                     help="tiles of 64 x 4096 to train the learned proposal on (0: skip)")
     ap.add_argument("--proposal-eval", type=int, default=8192, help="held-out evaluation tiles")
@@ -204,6 +208,9 @@ def main():
 
     spd.load()
     dev = torch.device("cuda:0")
+    if args.sweep:
+        print(json.dumps(sweep(dev)), flush=True)
+        return
     t = time.time()
     w = synth.ska_beam(n_dm=args.n_dm, n=args.n)
     x_host = w.rows()
@@ -469,6 +476,53 @@ def main():
     if prop is not None:
         out["proposal"] = prop
     print(json.dumps(out), flush=True)
+
+
+def sweep(dev) -> dict:
+    """Throughput over the paper's performance shapes (Section 5): n = 131072 with n_dm 256..8192,
+    n_dm = 256 with n = 2^15..2^20, L_end 256..16384 (IG(1) and BD-16, L_end 8192 unless swept),
+    plus the small exhaustive workload.  Noise inputs (the filter's work does not depend on the
+    data); each point is the median of 5 searches (planes and candidates)."""
+    import numpy as np
+    import torch
+    from paper_1910_08324_amd import spd
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def point(method, n_dm, n, l_end):
+        x = torch.randn((n_dm, n), generator=g, device=dev)
+        mu = torch.zeros(n_dm, device=dev)
+        sg = torch.ones(n_dm, device=dev)
+        r = spd.Runner(x, mu, sg, spd.Config(method, l_end, threshold=5.0), cand_cap=1 << 22)
+        r.search()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            e0.record()
+            r.search()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        del r, x
+        torch.cuda.empty_cache()
+        out = {"method": method, "n_dm": n_dm, "n": n, "l_end": l_end, "ms": round(ms, 4),
+               "dm_samples_per_s": n_dm * n / (ms * 1e-3), "rtf": n * T_SAMPLE / (ms * 1e-3)}
+        log(f"[bench] sweep {method} {n_dm}x{n} L_end {l_end}: {ms:.3f} ms")
+        return out
+
+    res = {"dm_count": [], "length": [], "l_end": []}
+    for m in ("ig1", "bd16"):
+        for n_dm in (256, 512, 1024, 2048, 4096, 8192):
+            res["dm_count"].append(point(m, n_dm, 131072, 8192))
+        for e in range(15, 21):
+            res["length"].append(point(m, 256, 1 << e, 8192))
+        for L in (256, 512, 1024, 2048, 4096, 8192, 16384):
+            res["l_end"].append(point(m, 1024, 131072, L))
+    res["small_exhaustive"] = point("exh", 64, 65536, 256)
+    return {"sweep": res, "unit_note": "ms per search (planes + candidates), one MI355X"}
 
 
 def batch_section(args, dev) -> dict:

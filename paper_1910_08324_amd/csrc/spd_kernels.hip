@@ -657,8 +657,11 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
         }
     }
 
-    // ---- recover the smallest width attaining the maximum inside the winning group
+    // ---- recover the smallest width attaining the maximum inside the winning group.  With a
+    // single block of widths the ring still holds the whole window (it was never refilled), so
+    // the replay reads the same values from LDS; otherwise it reloads them.
     int bw[4] = {0, 0, 0, 0};
+    const float *ring = reinterpret_cast<const float *>(ring4);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         if (best[v] == SPD_NEG_INF) continue;
@@ -668,7 +671,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
         for (int t = 0; t < kExhGroup; ++t) {
             const int L = Lb + t;
             if (L > Lw) break;
-            Xr += load_z(xr, sv + L - 1, n_in, mu, inv);
+            Xr += (nblk == 1) ? ring[4 * lane + v + L - 1] : load_z(xr, sv + L - 1, n_in, mu, inv);
             float snr = Xr * srow[L - 1];
             bool ok = L <= room[v];
             if (!DENSE) ok = ok && ((A.evalmask[(L - 1) >> 5] >> ((L - 1) & 31)) & 1u);
