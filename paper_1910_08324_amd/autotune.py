@@ -1,7 +1,8 @@
 """Autotuner of the cascade's launch shape per beam shape.
 
 For a search configuration and a beam length it times the candidate tile lengths (`segment`) and
-on-chip DIT depths (`step_levels`, levels computed per launch) with the library's per-launch HIP
+on-chip DIT depths (`step_levels`, levels computed per launch; for the exhaustive search only the
+number of 256-slot items per wave, as segment 256/512/1024) with the library's per-launch HIP
 event timer (spd_filter_timed) on a sample of rows, and keeps the fastest.  Results never depend
 on these choices (the planes and candidates are bitwise identical for every tile length and
 depth), so the tuner only trades speed.  A batch of beams is then split into groups of equal
@@ -21,6 +22,7 @@ from . import spd
 
 SEGMENTS = (2048, 3072, 4096, 6144, 8192)
 DEPTHS = (3, 4, 5, 6)
+EXH_SEGMENTS = (256, 512, 1024)     # exhaustive: 1, 2 or 4 items of 256 slots per wave
 GRIDS = (0, 4096, 8192, 16384)
 
 
@@ -75,18 +77,21 @@ class Tuner:
         x = torch.randn((self.rows, n), generator=g, device=device, dtype=torch.float32)
         mu = torch.zeros(self.rows, device=device)
         sg = torch.ones(self.rows, device=device)
+        if method == "exh":
+            shapes = [(T, 0) for T in EXH_SEGMENTS]
+        else:
+            shapes = [(T, J) for T in SEGMENTS for J in DEPTHS]
         measured = []
-        for T in SEGMENTS:
-            for J in DEPTHS:
-                cfg = spd.Config(method, l_end, threshold=threshold, segment=T, step_levels=J)
-                try:
-                    r = spd.Runner(x, mu, sg, cfg, cand_cap=1 << 16)
-                except spd.SpdError:
-                    continue                     # this tile cannot hold these levels
-                r.filter()
-                t = np.median([sum(r.filter_timed()) for _ in range(self.reps)])
-                measured.append((T, J, float(t)))
-                del r
+        for T, J in shapes:
+            cfg = spd.Config(method, l_end, threshold=threshold, segment=T, step_levels=J)
+            try:
+                r = spd.Runner(x, mu, sg, cfg, cand_cap=1 << 16)
+            except spd.SpdError:
+                continue                         # this tile cannot hold these levels
+            r.filter()
+            t = np.median([sum(r.filter_timed()) for _ in range(self.reps)])
+            measured.append((T, J, float(t)))
+            del r
         if not measured:
             raise RuntimeError(f"no launch shape plans for {method} L_end={l_end} n={n}")
         # shapes within `tolerance` of the fastest are ties under timing noise: take the one

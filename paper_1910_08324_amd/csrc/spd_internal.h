@@ -18,6 +18,7 @@ constexpr int kExhBlock = 512;        // widths per LDS window refill in the exh
 constexpr int kExhGroup = 64;         // widths per max-only group (argmax recovered afterwards)
 constexpr int kSlabCap = 64;          // pre-candidates kept per (level, row, tile): one per lane
 constexpr int kExhSlabCap = 16;       // pre-candidates kept per exhaustive work item
+constexpr int kExhItemsPerWave = 4;   // work items per wave when every width fits one block
 constexpr int kPeakWaves = 8192;      // waves of the peak-finder passes
 
 // One level of a cascade step.  The step's input series is y_{k0} (for the first step the
@@ -120,6 +121,7 @@ struct ExhArgs {
     int64_t pitch;
     int32_t n_dm, n_in, n_out, l_end;
     int32_t n_seg;
+    int32_t segs_per_wave;    // consecutive work items per wave (> 1 only when l_end <= kExhBlock)
     int32_t vec_ok;
     int32_t want_cand;
     float threshold;

@@ -569,11 +569,17 @@ template <bool DENSE>
 __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
     __shared__ float4 ring4[512];                  // 2048 floats
 
+    // A wave takes `per` consecutive work items of a row (several when every width fits one
+    // block of the ring, so each further item needs only 256 new samples, loaded while the
+    // previous item computes).  Ring position 0 holds sample `base`.
     const int lane = threadIdx.x;
-    const int d = blockIdx.x / A.n_seg;
-    const int g = blockIdx.x - d * A.n_seg;
+    const int per = A.segs_per_wave;
+    const int waves_per_row = (A.n_seg + per - 1) / per;
+    const int d = blockIdx.x / waves_per_row;
+    const int g0 = (blockIdx.x - d * waves_per_row) * per;
     if (d >= A.n_dm) return;
-    const int s0 = g * kExhSlots;
+    const int g_end = min(g0 + per, A.n_seg);
+    const int base = g0 * kExhSlots;
     const float *xr = A.x + (int64_t)d * A.ld;
     const float *srow = A.scale + (int64_t)d * A.scale_ld;     // this row's 1/sigma(L) factors
     const float mu = A.mean[d];
@@ -581,8 +587,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
     const int Lw = A.l_end;
     const int n_in = A.n_in;
 
-    auto load4 = [&](int j) -> float4 {          // z[s0 + j .. s0 + j + 3], j multiple of 4
-        const int r = s0 + j;
+    auto load4 = [&](int r) -> float4 {          // z[r .. r + 3], r a multiple of 4
         float4 v;
         if (A.vec_ok && r + 3 < n_in) {
             v = *reinterpret_cast<const float4 *>(xr + r);
@@ -602,9 +607,19 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int j = q * 256 + lane * 4;
-        ring4[j >> 2] = load4(j);
+        ring4[j >> 2] = load4(base + j);
     }
+    int loaded_to = base + 1024;
     __syncthreads();
+
+    const int nblk = (Lw + kExhBlock - 1) / kExhBlock;
+    for (int g = g0; g < g_end; ++g) {
+    const int s0 = g * kExhSlots;
+    const int ro4 = (s0 - base) >> 2;              // ring offset (float4) of this item's window
+    // the next item's window reaches 256 samples further: fetch them now, store after this item
+    const bool fetch = (g + 1 < g_end) && (s0 + kExhSlots + 768 > loaded_to);
+    float4 nx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (fetch) nx = load4(loaded_to + lane * 4);
 
     float X[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     float best[4] = {SPD_NEG_INF, SPD_NEG_INF, SPD_NEG_INF, SPD_NEG_INF};
@@ -614,14 +629,13 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) room[v] = n_in - (s0 + 4 * lane + v);
 
-    const int nblk = (Lw + kExhBlock - 1) / kExhBlock;
     for (int b = 0; b < nblk; ++b) {
         const bool refill = (b + 1 < nblk);
         float4 pf0, pf1;
         const int jn = b * kExhBlock + 1024;
         if (refill) {
-            pf0 = load4(jn + lane * 4);
-            pf1 = load4(jn + 256 + lane * 4);
+            pf0 = load4(s0 + jn + lane * 4);
+            pf1 = load4(s0 + jn + 256 + lane * 4);
         }
         for (int gi = 0; gi < kExhBlock / kExhGroup; ++gi) {
             const int L0 = b * kExhBlock + gi * kExhGroup + 1;
@@ -635,7 +649,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
                 Xs[v] = X[v];
                 gm[v] = SPD_NEG_INF;
             }
-            const int jb4 = lane + ((L0 - 1) >> 2);
+            const int jb4 = ro4 + lane + ((L0 - 1) >> 2);
             if (fast)
                 exh_group<false, DENSE>(ring4, jb4, L0, srow, A.evalmask, Lw, room, X, gm);
             else
@@ -671,7 +685,8 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
         for (int t = 0; t < kExhGroup; ++t) {
             const int L = Lb + t;
             if (L > Lw) break;
-            Xr += (nblk == 1) ? ring[4 * lane + v + L - 1] : load_z(xr, sv + L - 1, n_in, mu, inv);
+            Xr += (nblk == 1) ? ring[(4 * ro4 + 4 * lane + v + L - 1) & 2047]
+                              : load_z(xr, sv + L - 1, n_in, mu, inv);
             float snr = Xr * srow[L - 1];
             bool ok = L <= room[v];
             if (!DENSE) ok = ok && ((A.evalmask[(L - 1) >> 5] >> ((L - 1) & 31)) & 1u);
@@ -737,6 +752,12 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
             }
         }
         if (lane == 0) A.slab_cnt[(int64_t)d * A.n_seg + g] = total;
+    }
+    if (fetch) {
+        ring4[(((loaded_to - base) >> 2) + lane) & 511] = nx;
+        loaded_to += 256;
+    }
+    __syncthreads();
     }
 }
 
@@ -1030,7 +1051,8 @@ uint64_t family_mask(int fam, int pattern) {
 }
 
 int launch_exhaustive(const ExhArgs &a, bool dense, void *stream) {
-    const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_seg));
+    const int64_t per_row = (a.n_seg + a.segs_per_wave - 1) / a.segs_per_wave;
+    const dim3 grid((unsigned)((int64_t)a.n_dm * per_row));
     if (dense)
         hipLaunchKernelGGL(exh_kernel<true>, grid, dim3(64), 0, (hipStream_t)stream, a);
     else

@@ -131,7 +131,9 @@ def test_plan_geometry(lib):
     (spd.Config("exh", 10, widths=[11]), (1, 10, 10)),
     (spd.Config("exh", 20000, widths=[1, 2]), (1, 10, 10)),      # list mode capped at 16384
     (spd.Config("exh", 10, planes=False, candidates=False), (1, 10, 10)),
-    (spd.Config("exh", 10, segment=512), (1, 10, 10)),
+    (spd.Config("exh", 10, segment=768), (1, 10, 10)),            # 3 items per wave
+    (spd.Config("exh", 10, segment=2048), (1, 10, 10)),
+    (spd.Config("exh", 513, segment=512), (1, 1000, 1000)),       # widths beyond one LDS window
     (spd.Config("ig1", 64, segment=1000), (1, 10, 10)),
     (spd.Config("ig1", 64), (1, 10, 11)),                       # n_out > n_in
     (spd.Config("ig1", 64), (0, 10, 10)),
@@ -177,7 +179,7 @@ def test_search_argument_errors_before_any_launch(lib):
 def test_plan_accepts_wide_range(lib, method):
     """The planner finds a launch geometry (and passes its own LDS-bounds self-check) for every
     L_end, row length and tile size in range."""
-    segs = [0] if method == "exh" else [0, 256, 512, 1024, 2048, 4096, 8192, 16384]
+    segs = [0, 256, 512, 1024] if method == "exh" else [0, 256, 512, 1024, 2048, 4096, 8192, 16384]
     for l_end in (1, 2, 5, 64, 255, 256, 1000, 4096, 8192, 8193, 30000, 65535):
         for n in (1, 7, 1000, 4097, 65536, 262144, 1 << 22):
             for seg in segs:
@@ -186,7 +188,9 @@ def test_plan_accepts_wide_range(lib, method):
                     info = spd.plan(cfg, 3, n, n)
                 except spd.SpdError as e:
                     # a fixed tile too short for the widest levels is the only allowed refusal
+                    # (exhaustive: more than one item per wave with widths beyond 512)
                     assert seg != 0 and e.status == spd.SPD_EINVAL, (l_end, n, seg)
+                    assert method != "exh" or (seg > 256 and l_end > 512), (l_end, n, seg)
                     continue
                 assert info.workspace_bytes > 0
 

@@ -126,7 +126,8 @@ def test_t0_offsets_candidate_starts(dev, method):
 
 
 @pytest.mark.parametrize("method,segs", [("ig1", [256, 1024, 2048]), ("bd16", [1024, 2048]),
-                                         ("ig3", [512, 3072]), ("bd32", [1024, 2048])])
+                                         ("ig3", [512, 3072]), ("bd32", [1024, 2048]),
+                                         ("exh", [256, 512, 1024])])
 def test_tile_invariance_bitwise(dev, method, segs):
     """Results do not depend on how time is split into work items (bit for bit)."""
     from paper_1910_08324_amd import spd
@@ -188,6 +189,15 @@ def test_dense_fallback_when_slabs_overflow(dev, method, l_end):
     parity.check_planes(P, R, x, mu, sg, n, what=method)
     nc, nr = parity.check_candidates(C, R, 3.0, what=method)
     assert nc > 1000
+
+
+@pytest.mark.parametrize("seg,n,l_end", [(1024, 20011, 512), (1024, 700, 300), (512, 3000, 1),
+                                         (1024, 9001, 64)])
+def test_exhaustive_items_per_wave_parity(dev, seg, n, l_end):
+    """Several 256-slot items per wave (the LDS window slides on between them): ragged last
+    wave, a row shorter than one wave's items, L_end 1 and the widest single window."""
+    full_check(dev, "exh", l_end, 4, n, 31 + l_end, segment=seg,
+               pulses=[synth.Pulse(2, n // 2, max(1, l_end // 3), 12.0)])
 
 
 def test_exhaustive_width_list(dev):
