@@ -82,7 +82,8 @@ extern "C" {
  *   segment         samples per work item along time (0 = chosen by the library).  Results do not
  *                   depend on it.  BoxDIT / IGRID: a multiple of 256 in 256..32768 that leaves
  *                   every launch of the level cascade room for its halo and its on-chip buffers
- *                   (spd_plan returns SPD_EINVAL otherwise); exhaustive: 256 only.
+ *                   (spd_plan returns SPD_EINVAL otherwise); exhaustive: 256, or 512 / 1024 (a wave
+ *                   takes 2 / 4 consecutive 256-sample items) when L_end <= 512.
  *   step_levels     BoxDIT / IGRID: separation levels computed on chip per kernel launch, 1..6,
  *                   or 0 for the library's choice (4, fewer if a tile's buffers would not fit).
  *                   Results do not depend on it.  Exhaustive: must be 0.
