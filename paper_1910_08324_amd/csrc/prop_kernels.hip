@@ -564,7 +564,7 @@ __global__ void labels_kernel(const float *e, const float *l, int32_t n, float t
 
 // ---------------------------------------------------------------------------------------
 // Fused inference: one work-group per row runs the three convolutions with the activations in
-// LDS (features 4.2 KB, two activation buffers of 16.8 KB), then the read-out; only the
+// LDS (features 4.2 KB, two activation buffers of 21 KB), then the read-out; only the
 // features come from HBM.  Each row leaves its read-out maximum and sum of exp(s - max); a
 // second kernel combines a tile's 64 rows into the logit.  The MFMA sequence is the unfused
 // kernels' one, so the activations are bitwise the same.
@@ -578,12 +578,21 @@ struct InferArgs {
     int32_t rows;
 };
 
-// one layer of a row held in LDS: out = relu(W in + b), 2 tiles of 32 positions per wave
+// Activation rows in LDS: padded position pp keeps its 32 channels (four 16-byte chunks) in a
+// row of 40 bf16 (80 bytes).  16-byte loads of one chunk by any 8 or 16 consecutive positions
+// (the MFMA operand and the read-out) then fall in distinct LDS banks, with 32 or 64 banks;
+// a 64-byte stride puts four positions on the same banks.
+constexpr int ACT_LD = CH + 8;
+__device__ __forceinline__ int act_at(int pp, int c) { return pp * ACT_LD + (c << 3); }
+
+// one layer of a row held in LDS: out = relu(W in + b), 2 tiles of 32 positions per wave.  The
+// layer-1 input (8 features per position, 16 bytes) is a plain row; wider inputs are padded.
 template <int CI>
 __device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, const float *bias,
                                          uint16_t *out, int wave, int l) {
     constexpr int KS = (TAPS * CI + 15) / 16;
     constexpr int KWC = KS * 16;
+    static_assert(CI == FCH || CI == CH, "layer inputs are the features or an activation row");
     const int h = l >> 5;
     const int n = l & 31;
     bf16x8 wa[KS];
@@ -597,10 +606,13 @@ __device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, 
         for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const bf16x8 b = load8(in + (p0 + n) * CI + 16 * s + 8 * h);
+            // k = 16 s + 8 h: tap s / 2, channels 16 (s % 2) + 8 h .. + 7 of position p0 + n + tap
+            const uint16_t *src = CI == CH ? in + act_at(p0 + n + (s >> 1), 2 * (s & 1) + h)
+                                           : in + (p0 + n) * CI + 16 * s + 8 * h;
+            const bf16x8 b = load8(src);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[s], b, acc, 0, 0, 0);
         }
-        uint16_t *o = out + (p0 + n + 2) * CH;
+        const int po = p0 + n + 2;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             uint16_t hv[4];
@@ -609,7 +621,7 @@ __device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, 
                 const int co = 8 * g + 4 * h + j;
                 hv[j] = to_bf16(fmaxf(acc[4 * g + j] + bias[co], 0.0f));
             }
-            *reinterpret_cast<uint2 *>(o + 8 * g + 4 * h) =
+            *reinterpret_cast<uint2 *>(out + act_at(po, g) + 4 * h) =
                 make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
                            (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
         }
@@ -618,8 +630,8 @@ __device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, 
 
 __global__ __launch_bounds__(256) void infer_kernel(const InferArgs A) {
     __shared__ __attribute__((aligned(16))) uint16_t f[RP * FCH];
-    __shared__ __attribute__((aligned(16))) uint16_t a[RP * CH];
-    __shared__ __attribute__((aligned(16))) uint16_t b[RP * CH];
+    __shared__ __attribute__((aligned(16))) uint16_t a[RP * ACT_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t b[RP * ACT_LD];
     __shared__ float red[8];
     const int r = blockIdx.x;
     if (r >= A.rows) return;
@@ -633,8 +645,8 @@ __global__ __launch_bounds__(256) void infer_kernel(const InferArgs A) {
     for (int i = tid; i < 6 * CH / 8; i += 256) {
         const int pos = i / (CH / 8), part = i - pos * (CH / 8);
         const int pp = pos < 2 ? pos : POS + pos;
-        reinterpret_cast<uint4 *>(a)[pp * (CH / 8) + part] = make_uint4(0u, 0u, 0u, 0u);
-        reinterpret_cast<uint4 *>(b)[pp * (CH / 8) + part] = make_uint4(0u, 0u, 0u, 0u);
+        *reinterpret_cast<uint4 *>(a + act_at(pp, part)) = make_uint4(0u, 0u, 0u, 0u);
+        *reinterpret_cast<uint4 *>(b + act_at(pp, part)) = make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
     conv_lds<FCH>(f, A.wb.w1, A.params + SPD_PROP_OFF_B1, a, wave, l);
@@ -645,7 +657,16 @@ __global__ __launch_bounds__(256) void infer_kernel(const InferArgs A) {
     __syncthreads();
     // read-out of position tid, then the row's max and sum of exp(s - max)
     float act[CH];
-    load_act(a + (tid + 2) * CH, act);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(a + act_at(tid + 2, q));
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            act[8 * q + 2 * e] = __uint_as_float(w[e] << 16);
+            act[8 * q + 2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
+        }
+    }
     const float *wh = A.params + SPD_PROP_OFF_WH;
     float sv = 0.0f;
 #pragma unroll

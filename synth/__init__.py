@@ -108,7 +108,7 @@ def draw_rect_pulses(n_dm: int, n: int, count: int, seed: int, width_range=(1, 6
                      snr_range=(6.0, 30.0), margin: int = 256) -> List[Pulse]:
     """`count` rectangular pulses in distinct rows; S ~ U{lo..hi}, C ~ U[lo, hi)."""
     rng = _pulse_rng(seed)
-    rows = rng.choice(n_dm, size=count, replace=False)
+    rows = rng.choice(n_dm, size=count, replace=count > n_dm)   # distinct rows while they last
     out = []
     for d in sorted(int(r) for r in rows):
         S = int(rng.integers(width_range[0], width_range[1] + 1))
@@ -120,9 +120,9 @@ def draw_rect_pulses(n_dm: int, n: int, count: int, seed: int, width_range=(1, 6
 
 def draw_gauss_pulses(n_dm: int, n: int, count: int, seed: int, fwhm_range=(1.0, 4096.0),
                       snr_range=(5.0, 50.0), margin: int = 8192) -> List[Pulse]:
-    """`count` Gaussian pulses in distinct rows; FWHM log-uniform, C ~ U[lo, hi)."""
+    """`count` Gaussian pulses (in distinct rows when count <= n_dm); FWHM log-uniform, C ~ U[lo, hi)."""
     rng = _pulse_rng(seed)
-    rows = rng.choice(n_dm, size=count, replace=False)
+    rows = rng.choice(n_dm, size=count, replace=count > n_dm)   # distinct rows while they last
     out = []
     lo, hi = math.log(fwhm_range[0]), math.log(fwhm_range[1])
     for d in sorted(int(r) for r in rows):
