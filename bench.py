@@ -180,7 +180,7 @@ def main():
                     help="the paper's performance shapes instead of the standard line: DM-count, "
                          "length and L_end sweeps for IG(1) and BD-16, and the small exhaustive "
                          "workload (64 x 65536, widths 1..256)")
-    ap.add_argument("--proposal-tiles", type=int, default=65536,
+    ap.add_argument("--proposal-tiles", type=int, default=1000000,
                     help="tiles of 64 x 4096 to train the learned proposal on (0: skip)")
     ap.add_argument("--proposal-eval", type=int, default=8192, help="held-out evaluation tiles")
     ap.add_argument("--proposal-batch", type=int, default=256)

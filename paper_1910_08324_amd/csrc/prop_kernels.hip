@@ -478,9 +478,32 @@ struct RedArgs {
     int32_t n_waves, n_tiles;
 };
 
-__global__ void reduce_kernel(const RedArgs A) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= SPD_PROP_NPARAMS) return;
+// Sum of src[w * stride] over w in [w0, w1), in increasing w, with 8 loads in flight.
+__device__ __forceinline__ float ordered_sum(const float *src, int64_t stride, int w0, int w1) {
+    float g = 0.0f;
+    int w = w0;
+    for (; w + 8 <= w1; w += 8) {
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = src[(int64_t)(w + q) * stride];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) g += v[q];
+    }
+    for (; w < w1; ++w) g += src[(int64_t)w * stride];
+    return g;
+}
+
+// A work-group takes RED_PARAMS gradient entries; each entry's partials are cut into RED_CHUNKS
+// consecutive ranges summed in order by separate threads, and the range sums are added in order.
+constexpr int RED_PARAMS = 8;
+constexpr int RED_CHUNKS = 32;
+
+__global__ __launch_bounds__(256) void reduce_kernel(const RedArgs A) {
+    __shared__ float part[RED_CHUNKS][RED_PARAMS];
+    __shared__ float lsum[256];
+    const int j = threadIdx.x % RED_PARAMS;
+    const int c = threadIdx.x / RED_PARAMS;
+    const int i = blockIdx.x * RED_PARAMS + j;
     const float *src = nullptr;
     int stride = 0, idx = 0, count = A.n_waves;
     if (i < SPD_PROP_OFF_B1) {
@@ -498,14 +521,26 @@ __global__ void reduce_kernel(const RedArgs A) {
     } else if (i <= SPD_PROP_OFF_BH) {
         src = A.hpart; stride = CH + 1; idx = i - SPD_PROP_OFF_WH; count = A.n_tiles;
     }
-    float g = 0.0f;
-    if (src)
-        for (int w = 0; w < count; ++w) g += src[(int64_t)w * stride + idx];
-    A.grads[i] = g;
-    if (i == 0) {
-        float L = 0.0f;
-        for (int t = 0; t < A.n_tiles; ++t) L += A.loss_t[t];
-        A.loss[0] = L / (float)A.n_tiles;
+    const int w0 = (int)((int64_t)c * count / RED_CHUNKS);
+    const int w1 = (int)((int64_t)(c + 1) * count / RED_CHUNKS);
+    part[c][j] = src ? ordered_sum(src + idx, stride, w0, w1) : 0.0f;
+    __syncthreads();
+    if (c == 0 && i < SPD_PROP_NPARAMS) {
+        float g = 0.0f;
+        for (int q = 0; q < RED_CHUNKS; ++q) g += part[q][j];
+        A.grads[i] = g;
+    }
+    if (blockIdx.x == 0) {
+        // mean loss: 256 ordered ranges of the tiles, then the range sums in order
+        const int t0 = (int)((int64_t)threadIdx.x * A.n_tiles / 256);
+        const int t1 = (int)((int64_t)(threadIdx.x + 1) * A.n_tiles / 256);
+        lsum[threadIdx.x] = ordered_sum(A.loss_t, 1, t0, t1);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float L = 0.0f;
+            for (int q = 0; q < 256; ++q) L += lsum[q];
+            A.loss[0] = L / (float)A.n_tiles;
+        }
     }
 }
 
@@ -537,21 +572,42 @@ struct TileMaxArgs {
     int64_t pitch[SPD_MAX_LEVELS];
     int64_t slots[SPD_MAX_LEVELS];
     int32_t n_levels, rows_per_tile, n_tiles;
+    int32_t vec_ok;            // planes 16-byte aligned: float4 loads
 };
 
-__global__ __launch_bounds__(256) void tile_max_kernel(const TileMaxArgs A) {
+// A float (never NaN here) as a signed integer of the same order: non-negative floats keep their
+// bits, negative ones have the 31 magnitude bits inverted.  The map is its own inverse.
+__device__ __forceinline__ int32_t order_key(int32_t bits) { return bits >= 0 ? bits : bits ^ 0x7FFFFFFF; }
+
+__global__ void tile_init_kernel(int32_t *key, int32_t n_tiles) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_tiles) key[t] = order_key(__float_as_int(-__builtin_huge_valf()));
+}
+
+// one work-group per DM row: the row's maximum over every level, merged into its tile's entry
+// with an integer atomic maximum on the order key
+__global__ __launch_bounds__(256) void tile_max_kernel(const TileMaxArgs A, int32_t *key) {
     __shared__ float sh[4];
-    const int t = blockIdx.x;
-    if (t >= A.n_tiles) return;
+    const int d = blockIdx.x;
+    if (d >= A.n_tiles * A.rows_per_tile) return;
     float mx = -__builtin_huge_valf();
     for (int lv = 0; lv < A.n_levels; ++lv) {
-        for (int j = 0; j < A.rows_per_tile; ++j) {
-            const float *Y = A.snr + A.off[lv] + ((int64_t)t * A.rows_per_tile + j) * A.pitch[lv];
-            for (int64_t s = threadIdx.x; s < A.slots[lv]; s += 256) mx = fmaxf(mx, Y[s]);
+        const float *Y = A.snr + A.off[lv] + (int64_t)d * A.pitch[lv];
+        const int64_t n = A.slots[lv];
+        const int64_t n4 = A.vec_ok ? n >> 2 : 0;
+        for (int64_t q = threadIdx.x; q < n4; q += 256) {
+            const float4 v = reinterpret_cast<const float4 *>(Y)[q];
+            mx = fmaxf(mx, fmaxf(fmaxf(v.x, v.y), fmaxf(v.z, v.w)));
         }
+        for (int64_t s = 4 * n4 + threadIdx.x; s < n; s += 256) mx = fmaxf(mx, Y[s]);
     }
     mx = block_max(mx, sh);
-    if (threadIdx.x == 0) A.out[t] = mx;
+    if (threadIdx.x == 0) atomicMax(key + d / A.rows_per_tile, order_key(__float_as_int(mx)));
+}
+
+__global__ void tile_fin_kernel(int32_t *key, int32_t n_tiles) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_tiles) reinterpret_cast<float *>(key)[t] = __int_as_float(order_key(key[t]));
 }
 
 __global__ void labels_kernel(const float *e, const float *l, int32_t n, float thr, float m,
@@ -914,7 +970,7 @@ int spd_prop_backward(const float *params, const uint16_t *feat, const float *la
     w.part = B.part1;
     SPDP_LAUNCH(wgrad_kernel<FCH>, dim3(wg_blocks), dim3(256), 0, s, w);
     RedArgs r{B.part1, B.part2, B.part3, B.hpart, B.loss_t, grads, loss, L.n_waves, n_tiles};
-    SPDP_LAUNCH(reduce_kernel, dim3((SPD_PROP_NPARAMS + 255) / 256), dim3(256), 0, s, r);
+    SPDP_LAUNCH(reduce_kernel, dim3((SPD_PROP_NPARAMS + RED_PARAMS - 1) / RED_PARAMS), dim3(256), 0, s, r);
     return SPD_OK;
 }
 
@@ -946,12 +1002,20 @@ int spd_tile_max(const float *snr, const spd_plan_info *info, int32_t n_dm, int3
     a.n_levels = info->n_levels;
     a.rows_per_tile = rows_per_tile;
     a.n_tiles = n_dm / rows_per_tile;
+    a.vec_ok = ((uintptr_t)snr & 15) == 0;
     for (int i = 0; i < info->n_levels; ++i) {
         a.off[i] = info->plane_offset[i];
         a.pitch[i] = info->plane_pitch[i];
         a.slots[i] = info->plane_slots[i];
+        if ((a.off[i] | a.pitch[i]) & 3) a.vec_ok = 0;
     }
-    SPDP_LAUNCH(tile_max_kernel, dim3(a.n_tiles), dim3(256), 0, static_cast<hipStream_t>(hip_stream), a);
+    // the output holds the order keys until the last pass turns them back into floats
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int32_t *key = reinterpret_cast<int32_t *>(tile_max);
+    const dim3 tg((a.n_tiles + 255) / 256);
+    SPDP_LAUNCH(tile_init_kernel, tg, dim3(256), 0, st, key, a.n_tiles);
+    SPDP_LAUNCH(tile_max_kernel, dim3(n_dm), dim3(256), 0, st, a, key);
+    SPDP_LAUNCH(tile_fin_kernel, tg, dim3(256), 0, st, key, a.n_tiles);
     return SPD_OK;
 }
 
