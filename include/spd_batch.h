@@ -71,6 +71,17 @@ int spd_batch_search(const spd_params *params, int32_t n_beams, const spd_beam *
                      const void *table_dev, void *workspace, int64_t workspace_bytes,
                      int32_t grid, void *hip_stream);
 
+/*
+ * spd_copy_rows: dst[r][c] = src[r][c] for r < n_rows, c < n_cols.  dst and src are DEVICE float
+ * arrays with row strides ld_dst, ld_src >= n_cols (in floats); the two must not overlap.  A
+ * streaming search appends each arriving block of a beam after the samples it keeps on the
+ * device with this copy (16-byte vector accesses when both sides allow them).  n_cols == 0 or
+ * n_rows == 0 enqueues nothing.  Asynchronous on the stream; SPD_EINVAL for negative sizes, a
+ * stride below n_cols or a NULL pointer with work to do, SPD_EHIP for a failed launch.
+ */
+int spd_copy_rows(float *dst, int64_t ld_dst, const float *src, int64_t ld_src, int32_t n_rows,
+                  int32_t n_cols, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,8 @@ LIB = os.path.join(PKG, "libspd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = [os.path.join(CSRC, "spd_kernels.hip"), os.path.join(CSRC, "spd_api.cpp"),
-           os.path.join(CSRC, "prop_kernels.hip"), os.path.join(CSRC, "msd_kernels.hip")]
+           os.path.join(CSRC, "prop_kernels.hip"), os.path.join(CSRC, "msd_kernels.hip"),
+           os.path.join(CSRC, "stream_kernels.hip")]
 
 FLAGS = [
     "--offload-arch=gfx950",

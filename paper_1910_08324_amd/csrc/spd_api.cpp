@@ -288,9 +288,12 @@ int plan_step(const Search &s, int k0, int J, int T, StepPlan *st) {
     return st->lds_bytes;
 }
 
+// ref_out: the output length the tile lengths are sized for (0: n_out).  A batch passes its
+// longest beam's, so that every beam gets the same launch geometry.
 int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in, int32_t n_out,
-                Layout *L) {
+                Layout *L, int64_t ref_out = 0) {
     if (n_dm < 1 || n_in < 1 || n_out < 1 || n_out > n_in) return SPD_EINVAL;
+    if (ref_out <= 0) ref_out = n_out;
     if (p->rho && (p->n_rho < 1 || p->n_rho > SPD_MAX_LEVELS)) return SPD_EINVAL;
     if (!p->rho && p->n_rho != 0) return SPD_EINVAL;
     if ((int64_t)n_in > (int64_t)INT32_MAX - (1 << 20)) return SPD_EINVAL;
@@ -355,6 +358,19 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
             StepPlan st;
             int J = std::min(jmax, K + 1 - k0);
             int Tj = T;
+            // a step whose first level has fewer slots than a tile gets a shorter tile (a multiple
+            // of 256), since one long tile per row would idle most of its threads; results do not
+            // depend on the tile length.  A fixed segment still sets the first launch's tile.
+            if (k0 > 0 || !fixed_T) {
+                const int64_t want =
+                    std::max<int64_t>(256, round_up(ceil_div(ref_out, (int64_t)1 << k0), 256));
+                if (want < Tj) {
+                    StepPlan trial;
+                    int l2 = plan_step(s, k0, J, (int)want, &trial);
+                    if (l2 >= 0 && p->rho) l2 += spd::kStepMaxLevels * spd::kMaxLevelWidths * 4;
+                    if (l2 >= 0 && l2 <= 60 * 1024) Tj = (int)want;
+                }
+            }
             int lds = -1;
             for (;;) {
                 lds = plan_step(s, k0, J, Tj, &st);
@@ -734,9 +750,11 @@ int batch_plan(const spd_params *params, int32_t n_beams, const spd_beam *beams,
     if (st != SPD_OK) return st;
     B->L.resize(n_beams);
     B->ws_off.resize(n_beams);
-    int64_t off = 0;
+    int64_t off = 0, ref_out = 1;
+    for (int b = 0; b < n_beams; ++b) ref_out = std::max<int64_t>(ref_out, beams[b].n_out);
     for (int b = 0; b < n_beams; ++b) {
-        st = make_layout(params, B->s, beams[b].n_dm, beams[b].n_in, beams[b].n_out, &B->L[b]);
+        st = make_layout(params, B->s, beams[b].n_dm, beams[b].n_in, beams[b].n_out, &B->L[b],
+                         ref_out);
         if (st != SPD_OK) return st;
         const std::vector<StepPlan> &S = B->L[b].steps;
         const std::vector<StepPlan> &S0 = B->L[0].steps;

@@ -106,7 +106,8 @@ class StreamServer:
     def __init__(self, method: str = "ig1", l_end: int = 8192, threshold: float = 5.0,
                  max_block: int = 8192, hbm_budget: int = 64 << 30, slots: int = 3,
                  max_beams_per_batch: int = 16, cand_cap: int = 1 << 15, segment: int = 0,
-                 step_levels: int = 0, coalesce: int = 4, device="cuda"):
+                 step_levels: int = 0, coalesce: int = 4, cand_prefix: int = 4096,
+                 device="cuda"):
         import torch
         self.device = torch.device(device)
         self.cfg = spd.Config(method, l_end, threshold=threshold, planes=False, candidates=True,
@@ -125,6 +126,7 @@ class StreamServer:
         self.budget = int(hbm_budget)
         self.max_reqs = int(max_beams_per_batch)
         self.cand_cap = int(cand_cap)
+        self.cand_prefix = max(1, min(self.cand_cap, int(cand_prefix)))
         self.n_slots = int(slots)
         self.slots: List[_Slot] = []
         self.beams: Dict[int, _Beam] = {}
@@ -195,7 +197,12 @@ class StreamServer:
             if total > self.cand_cap:
                 raise RuntimeError(f"beam {grp[0].beam} blocks {grp[0].index}..{grp[-1].index}: "
                                    f"{total} candidates exceed the capacity {self.cand_cap}")
-            c = s.cand_host[i, : total * spd.CANDIDATE_DTYPE.itemsize].numpy().view(spd.CANDIDATE_DTYPE)
+            nb = total * spd.CANDIDATE_DTYPE.itemsize
+            if total > self.cand_prefix:
+                # more than the prefix copied with the batch: fetch the rest now (the batch is done)
+                pre = self.cand_prefix * spd.CANDIDATE_DTYPE.itemsize
+                s.cand_host[i, pre: nb].copy_(s.cand[i, pre: nb])
+            c = s.cand_host[i, :nb].numpy().view(spd.CANDIDATE_DTYPE)
             for r in grp:
                 keep = (c["start"] >= r.region[0]) & (c["start"] < r.region[1])
                 self.results.append(Result(r.beam, r.index, r.region, c[keep].copy(), r.arrival,
@@ -260,13 +267,13 @@ class StreamServer:
         if b.t_end + B - b.buf_start > b.cap:
             src, dst = b.buf[b.active], b.buf[1 - b.active]
             n = b.t_end - keep_from
-            with torch.cuda.stream(stream):
-                dst[:, :n].copy_(src[:, keep_from - b.buf_start: keep_from - b.buf_start + n])
+            if n > 0:
+                spd.copy_rows(dst[:, :n], src[:, keep_from - b.buf_start: keep_from - b.buf_start + n],
+                              stream)
             b.active = 1 - b.active
             b.buf_start = keep_from
         off = b.t_end - b.buf_start
-        with torch.cuda.stream(stream):
-            b.buf[b.active][:, off: off + B].copy_(block)
+        spd.copy_rows(b.buf[b.active][:, off: off + B], block, stream)
         b.t_end += B
 
     def _launch(self, s: _Slot, groups: List[List[Request]], mem: int):
@@ -314,9 +321,13 @@ class StreamServer:
                                                  ctypes.c_void_p(s.table_dev.data_ptr()),
                                                  ctypes.c_void_p(s.ws.data_ptr()), s.ws.numel(), 0,
                                                  ctypes.c_void_p(st.cuda_stream)), "spd_batch_search")
+            # counts and the first cand_prefix candidates of every window come back with the
+            # batch; a window with more fetches the rest when it is retired
+            pre = self.cand_prefix * spd.CANDIDATE_DTYPE.itemsize
             with torch.cuda.stream(st):
                 s.count_host.copy_(s.count, non_blocking=True)
-                s.cand_host.copy_(s.cand, non_blocking=True)
+                for gi in range(len(groups)):
+                    s.cand_host[gi, :pre].copy_(s.cand[gi, :pre], non_blocking=True)
         s.groups = groups
         s.mem = mem
         s.busy = True

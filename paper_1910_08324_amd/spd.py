@@ -395,10 +395,25 @@ def _bind_batch(lib):
     lib.spd_batch_table.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(Beam), P, P, i64]
     lib.spd_batch_search.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(Beam), P, P, i64,
                                      i32, P]
-    for n in ("spd_batch_plan", "spd_batch_table", "spd_batch_search"):
+    lib.spd_copy_rows.argtypes = [P, i64, P, i64, i32, i32, P]
+    for n in ("spd_batch_plan", "spd_batch_table", "spd_batch_search", "spd_copy_rows"):
         getattr(lib, n).restype = ctypes.c_int
     lib._batch_bound = True
     return lib
+
+
+def copy_rows(dst, src, stream=None):
+    """dst[:, :] = src[:, :] for 2-D float32 device views of equal shape with unit column stride
+    (spd_copy_rows), on `stream` (default: the current stream)."""
+    import torch
+    if dst.dtype != torch.float32 or src.dtype != torch.float32 or dst.shape != src.shape \
+            or dst.dim() != 2 or dst.stride(1) != 1 or src.stride(1) != 1:
+        raise ValueError("copy_rows needs equal-shape 2-D float32 views with unit column stride")
+    st = stream if stream is not None else torch.cuda.current_stream(dst.device)
+    lib = _bind_batch(load())
+    _check(lib.spd_copy_rows(ctypes.c_void_p(dst.data_ptr()), dst.stride(0),
+                             ctypes.c_void_p(src.data_ptr()), src.stride(0), dst.shape[0],
+                             dst.shape[1], ctypes.c_void_p(st.cuda_stream)), "spd_copy_rows")
 
 
 class Batch:

@@ -274,3 +274,17 @@ def test_batch_plan_and_table_host(lib):
     assert L.spd_batch_plan(ctypes.byref(p), 0, arr, ctypes.byref(wsb), ctypes.byref(tb)) == spd.SPD_EINVAL
     assert L.spd_batch_search(ctypes.byref(p), len(shapes), arr, None, ctypes.c_void_p(256),
                               wsb.value, 0, None) == spd.SPD_EINVAL
+
+
+def test_copy_rows_argument_checks(lib):
+    """spd_copy_rows rejects bad sizes before any launch; empty copies do nothing."""
+    spd._bind_batch(lib)
+    P = ctypes.c_void_p
+    assert lib.spd_copy_rows(P(256), 10, P(512), 10, -1, 4, None) == spd.SPD_EINVAL
+    assert lib.spd_copy_rows(P(256), 10, P(512), 10, 2, -4, None) == spd.SPD_EINVAL
+    assert lib.spd_copy_rows(P(256), 3, P(512), 10, 2, 4, None) == spd.SPD_EINVAL
+    assert lib.spd_copy_rows(P(256), 10, P(512), 3, 2, 4, None) == spd.SPD_EINVAL
+    assert lib.spd_copy_rows(None, 10, P(512), 10, 2, 4, None) == spd.SPD_EINVAL
+    assert lib.spd_copy_rows(P(256), 10, P(512), 10, 70000, 4, None) == spd.SPD_EINVAL
+    assert lib.spd_copy_rows(None, 0, None, 0, 0, 0, None) == spd.SPD_OK
+    assert lib.spd_copy_rows(None, 0, None, 0, 3, 0, None) == spd.SPD_OK

@@ -119,3 +119,37 @@ def test_budget_limits_admission(S):
     # nothing whose window needs memory fits a 1-byte budget; blocks with empty regions pass
     assert all(r.region[0] == r.region[1] for r in srv.results)
     assert len(srv.queue) > 0
+
+
+@pytest.mark.parametrize("rows,cols,off_dst,off_src", [(3, 9001, 0, 0), (5, 4096, 4, 8),
+                                                        (2, 1000, 1, 3), (4, 8193, 7, 0),
+                                                        (1, 3, 2, 1)])
+def test_copy_rows_matches_slicing(S, rows, cols, off_dst, off_src):
+    """spd_copy_rows: bitwise the slice assignment, on the vector path (aligned) and the scalar
+    path, across 4096-column chunks and ragged tails, touching nothing outside the target."""
+    from paper_1910_08324_amd import spd
+    g = torch.Generator(device="cuda")
+    g.manual_seed(rows * 7 + cols)
+    src = torch.randn((rows, cols + off_src + 13), generator=g, device="cuda")
+    dst = torch.full((rows, cols + off_dst + 20), 7.5, device="cuda")
+    ref = dst.clone()
+    ref[:, off_dst: off_dst + cols] = src[:, off_src: off_src + cols]
+    spd.copy_rows(dst[:, off_dst: off_dst + cols], src[:, off_src: off_src + cols])
+    torch.cuda.synchronize()
+    assert torch.equal(dst, ref)
+
+
+def test_candidate_prefix_does_not_change_results(S):
+    """Windows with more candidates than the prefix copied back with the batch fetch the rest
+    at retirement: the results equal those with a large prefix."""
+    n_dm = 12
+    beams = {b: stream(b, n_dm, sizes_for(b, 5, seed=4), seed=4) for b in range(3)}
+    order = [(b, i) for i in range(5) for b in range(3)]
+    big = run(S, beams, order, cand_prefix=1 << 15)
+    small = run(S, beams, order, cand_prefix=1)
+    key = lambda r: (r.beam, r.index)
+    A, B = sorted(big.results, key=key), sorted(small.results, key=key)
+    assert len(A) == len(B) and sum(r.total > 1 for r in A) >= 3
+    for a, b in zip(A, B):
+        assert a.region == b.region and a.total == b.total
+        assert np.array_equal(a.candidates, b.candidates)
