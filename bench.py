@@ -191,6 +191,8 @@ def main():
     ap.add_argument("--batch-ws-gb", type=float, default=120.0, help="workspace budget per fused group")
     ap.add_argument("--serve-blocks", type=int, default=24,
                     help="blocks per beam of the streaming-server run (0: skip)")
+    ap.add_argument("--serve-coalesce", type=int, default=8,
+                    help="queued blocks of a beam searched as one window")
     ap.add_argument("--serve-speed", type=float, default=20.0,
                     help="arrival pacing of the served run, in multiples of real time")
     args = ap.parse_args()
@@ -627,7 +629,7 @@ def serve_section(args, dev) -> dict:
     def make():
         srv = serve.StreamServer(method=args.method, l_end=8192, threshold=5.0, max_block=8192,
                                  hbm_budget=64 << 30, slots=3, max_beams_per_batch=n_beams,
-                                 device=dev)
+                                 coalesce=args.serve_coalesce, device=dev)
         for b in range(n_beams):
             srv.open_beam(b, n_dm)
         return srv
@@ -644,7 +646,6 @@ def serve_section(args, dev) -> dict:
     for i in range(nb):
         for b in range(n_beams):
             srv.submit(b, blocks[b][i], arrival=t0)
-            srv.poll()
     srv.drain()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

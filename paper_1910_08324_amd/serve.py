@@ -16,13 +16,16 @@ boxcar spacing), as spd_search requires of t0.
 
 Continuous batching: requests (one per arriving block) wait in arrival order.  Whenever a
 batch slot is free, every beam with waiting blocks and no search in flight is admitted, with up
-to `coalesce` of its queued blocks searched as one window, as long as the windows' memory fits
-the HBM budget beside what is already in flight; the admitted windows run as ONE fused
-multi-beam search (spd_batch_search) on that slot's stream, and each block gets the candidates
-of its own region.  Several slots are in
-flight at once on separate streams, so requests that arrive while others run are admitted as
-slots and memory free up, and their work overlaps on the device.  A block's result depends only
-on its beam's stream, never on what it was batched with.
+to `coalesce` of its queued blocks searched as one window (a longer window spreads the
+look-ahead over more samples), as long as the batch's search workspace fits a free range of
+the workspace arena; the admitted windows run as ONE fused multi-beam search
+(spd_batch_search) on that slot's stream, and each block gets the candidates of its own
+region.  The arena is one device buffer of `hbm_budget` bytes (less if no set of full batches
+could use that much), so the workspace of everything in flight stays within the budget.  The
+beams' sample buffers (two of `cap` samples per row each) are beam state outside it.  Several
+slots are in flight at once on separate streams, so requests that arrive while others run are
+admitted as slots and memory free up, and their work overlaps on the device.  A block's result
+depends only on its beam's stream, never on what it was batched with.
 
 Everything numeric runs in libspd's kernels; this module only sequences launches, copies and
 events.
@@ -82,11 +85,44 @@ class _Beam:
         self.sigma = sigma if sigma is not None else torch.ones(n_dm, device=device)
 
 
+class _Arena:
+    """First-fit ranges (256-byte aligned) of one device buffer: the search workspaces of the
+    batches in flight.  Its size is the HBM budget (or less, if no set of batches could use
+    more), so whatever is admitted fits the budget by construction."""
+
+    def __init__(self, size: int, device):
+        import torch
+        self.size = size // 256 * 256
+        self.buf = torch.empty(max(256, self.size), dtype=torch.uint8, device=device)
+        self.used: List[Tuple[int, int]] = []          # (offset, bytes), by offset
+
+    def alloc(self, n: int) -> Optional[int]:
+        n = -(-max(1, n) // 256) * 256
+        at = 0
+        for i, (o, m) in enumerate(self.used):
+            if o - at >= n:
+                self.used.insert(i, (at, n))
+                return at
+            at = o + m
+        if self.size - at >= n:
+            self.used.append((at, n))
+            return at
+        return None
+
+    def free(self, off: int):
+        self.used = [u for u in self.used if u[0] != off]
+
+    @property
+    def in_use(self) -> int:
+        return sum(m for _, m in self.used)
+
+
 class _Slot:
-    def __init__(self, device, ws_bytes: int, table_bytes: int, max_reqs: int, cand_cap: int):
+    def __init__(self, device, table_bytes: int, max_reqs: int, cand_cap: int):
         import torch
         self.stream = torch.cuda.Stream(device=device)          # default priority
-        self.ws = torch.empty(max(256, ws_bytes), dtype=torch.uint8, device=device)
+        self.ws_off: Optional[int] = None
+        self.ws_bytes = 0
         self.table_host = torch.empty(table_bytes, dtype=torch.uint8, pin_memory=True)
         self.table_dev = torch.empty(table_bytes, dtype=torch.uint8, device=device)
         self.cand = torch.empty((max_reqs, cand_cap * spd.CANDIDATE_DTYPE.itemsize),
@@ -96,8 +132,8 @@ class _Slot:
         self.count_host = torch.empty(max_reqs, dtype=torch.int64, pin_memory=True)
         self.done = torch.cuda.Event()
         self.groups: List[List[Request]] = []
+        self.windows: List[Optional[Tuple[int, int, int]]] = []
         self.busy = False
-        self.mem = 0
 
 
 class StreamServer:
@@ -106,7 +142,7 @@ class StreamServer:
     def __init__(self, method: str = "ig1", l_end: int = 8192, threshold: float = 5.0,
                  max_block: int = 8192, hbm_budget: int = 64 << 30, slots: int = 3,
                  max_beams_per_batch: int = 16, cand_cap: int = 1 << 15, segment: int = 0,
-                 step_levels: int = 0, coalesce: int = 4, cand_prefix: int = 4096,
+                 step_levels: int = 0, coalesce: int = 8, cand_prefix: int = 4096,
                  device="cuda"):
         import torch
         self.device = torch.device(device)
@@ -132,7 +168,7 @@ class StreamServer:
         self.beams: Dict[int, _Beam] = {}
         self.queue: Deque[Request] = collections.deque()
         self.results: List[Result] = []
-        self.mem_in_flight = 0
+        self.arena: Optional[_Arena] = None
 
     # ------------------------------------------------------------------ set-up
     def open_beam(self, beam: int, n_dm: int, mean=None, sigma=None):
@@ -140,23 +176,24 @@ class StreamServer:
         if not self.slots:
             self._make_slots(n_dm)
 
-    def _window_plan(self, n_dm: int, n_in: int, n_out: int) -> int:
-        return int(spd.plan(self.cfg, n_dm, n_in, n_out).workspace_bytes)
-
-    def _make_slots(self, n_dm: int):
-        # size every slot for a full batch of the largest windows
-        n_in = self.cap
-        per = self._window_plan(n_dm, n_in, n_in) + 4096
-        arr = (spd.Beam * self.max_reqs)()
-        for i in range(self.max_reqs):
-            arr[i].x, arr[i].ld, arr[i].n_dm, arr[i].n_in, arr[i].n_out = 256, n_in, n_dm, n_in, n_in
+    def _batch_plan(self, dims: List[Tuple[int, int, int]]) -> Tuple[int, int]:
+        """Workspace and table bytes of a batch of windows (n_dm, n_in, n_out)."""
+        arr = (spd.Beam * len(dims))()
+        for i, (n_dm, n_in, n_out) in enumerate(dims):
+            arr[i].x, arr[i].ld, arr[i].n_dm, arr[i].n_in, arr[i].n_out = 256, n_in, n_dm, n_in, n_out
             arr[i].mean = arr[i].sigma = 256
         wsb, tb = ctypes.c_int64(), ctypes.c_int64()
-        spd._check(self.lib.spd_batch_plan(ctypes.byref(self.params), self.max_reqs, arr,
+        spd._check(self.lib.spd_batch_plan(ctypes.byref(self.params), len(dims), arr,
                                            ctypes.byref(wsb), ctypes.byref(tb)), "spd_batch_plan")
+        return int(wsb.value), int(tb.value)
+
+    def _make_slots(self, n_dm: int):
+        # descriptor tables sized for a full batch of the largest windows; the workspace arena for
+        # the budget, or for every slot holding such a batch if that is less
+        full, tb = self._batch_plan([(n_dm, self.cap, self.cap)] * self.max_reqs)
+        self.arena = _Arena(min(self.budget, self.n_slots * (full + 256)), self.device)
         for _ in range(self.n_slots):
-            self.slots.append(_Slot(self.device, int(wsb.value) + per, int(tb.value) + 4096,
-                                    self.max_reqs, self.cand_cap))
+            self.slots.append(_Slot(self.device, tb + 4096, self.max_reqs, self.cand_cap))
 
     # ------------------------------------------------------------------ requests
     def submit(self, beam: int, block, ready=None, arrival: Optional[float] = None):
@@ -207,8 +244,9 @@ class StreamServer:
                 keep = (c["start"] >= r.region[0]) & (c["start"] < r.region[1])
                 self.results.append(Result(r.beam, r.index, r.region, c[keep].copy(), r.arrival,
                                            now, total))
-        self.mem_in_flight -= s.mem
-        s.groups, s.busy, s.mem = [], False, 0
+        if s.ws_off is not None:
+            self.arena.free(s.ws_off)
+        s.groups, s.windows, s.busy, s.ws_off, s.ws_bytes = [], [], False, None, 0
 
     def _admit(self):
         while self.queue:
@@ -216,8 +254,8 @@ class StreamServer:
             if slot is None:
                 return
             groups: List[List[Request]] = []
+            windows: List[Optional[Tuple[int, int, int]]] = []
             taken = set()
-            mem = 0
             queued = list(self.queue)
             for qi, r in enumerate(queued):
                 if len(groups) >= self.max_reqs:
@@ -234,29 +272,40 @@ class StreamServer:
                     t += q.block.shape[1]
                     q.region = (r0, max(r0, self._region_end(t)))
                     r0 = q.region[1]
-                need = self._mem_of_window(b, grp[0].region[0], r0, t)
-                if self.mem_in_flight + mem + need > self.budget:
-                    break                        # first come, first served within the budget
                 groups.append(grp)
-                mem += need
+                windows.append(self._window(grp[0].region[0], r0, t))
+            # the batch's workspace must fit a free range of the arena (the budget): the latest
+            # groups wait until it does, first come first served
+            off, wsb = None, 0
+            while groups:
+                dims = [(self.beams[g[0].beam].n_dm, w[1], w[2])
+                        for g, w in zip(groups, windows) if w is not None]
+                if not dims:
+                    break
+                wsb, _ = self._batch_plan(dims)
+                off = self.arena.alloc(wsb)
+                if off is not None:
+                    break
+                groups.pop()
+                windows.pop()
             if not groups:
                 return
             for grp in groups:
                 for q in grp:
                     self.queue.remove(q)
-            self._launch(slot, groups, mem)
+            self._launch(slot, groups, windows, off, wsb)
 
     def _region_end(self, t_end: int) -> int:
         g = self.grain
         return ((t_end - self.l_end + 1 - g) // g) * g
 
-    def _mem_of_window(self, b: _Beam, r0: int, r1: int, t_end: int) -> int:
+    def _window(self, r0: int, r1: int, t_end: int) -> Optional[Tuple[int, int, int]]:
+        """(t0, n_in, n_out) of the window searched for region [r0, r1) once t_end samples are
+        in, or None for an empty region."""
         if r1 <= r0:
-            return 0
+            return None
         t0 = max(0, r0 - self.grain)
-        n_out = r1 + self.grain - t0
-        n_in = min(t_end, r1 + self.grain + self.l_end - 1) - t0
-        return self._window_plan(b.n_dm, n_in, n_out)
+        return t0, min(t_end, r1 + self.grain + self.l_end - 1) - t0, r1 + self.grain - t0
 
     def _append(self, b: _Beam, block, stream):
         """Copy a block after the beam's samples, first moving the samples the next window still
@@ -276,25 +325,23 @@ class StreamServer:
         spd.copy_rows(b.buf[b.active][:, off: off + B], block, stream)
         b.t_end += B
 
-    def _launch(self, s: _Slot, groups: List[List[Request]], mem: int):
+    def _launch(self, s: _Slot, groups: List[List[Request]],
+                windows: List[Optional[Tuple[int, int, int]]], ws_off: Optional[int], ws_bytes: int):
         import torch
         st = s.stream
         arr = (spd.Beam * len(groups))()
         n = 0
-        for gi, grp in enumerate(groups):
+        for gi, (grp, win) in enumerate(zip(groups, windows)):
             b = self.beams[grp[0].beam]
             b.busy = True
             for r in grp:
                 if r.ready is not None:
                     st.wait_event(r.ready)
                 self._append(b, r.block, st)
-            r0, r1 = grp[0].region[0], grp[-1].region[1]
-            b.r0 = r1
-            if r1 <= r0:
+            b.r0 = grp[-1].region[1]
+            if win is None:
                 continue
-            t0 = max(0, r0 - self.grain)
-            n_out = r1 + self.grain - t0
-            n_in = min(b.t_end, r1 + self.grain + self.l_end - 1) - t0
+            t0, n_in, n_out = win
             x = b.buf[b.active]
             a = arr[n]
             n += 1
@@ -309,18 +356,18 @@ class StreamServer:
             wsb, tb = ctypes.c_int64(), ctypes.c_int64()
             spd._check(self.lib.spd_batch_plan(ctypes.byref(self.params), n, arr,
                                                ctypes.byref(wsb), ctypes.byref(tb)), "spd_batch_plan")
-            if wsb.value > s.ws.numel() or tb.value > s.table_dev.numel():
-                raise RuntimeError("batch slot too small for the admitted windows")
-            spd._check(self.lib.spd_batch_table(ctypes.byref(self.params), n, arr,
-                                                ctypes.c_void_p(s.ws.data_ptr()),
+            if ws_off is None or wsb.value > ws_bytes or tb.value > s.table_dev.numel():
+                raise RuntimeError("admitted batch does not match its planned workspace")
+            ws = ctypes.c_void_p(self.arena.buf.data_ptr() + ws_off)
+            spd._check(self.lib.spd_batch_table(ctypes.byref(self.params), n, arr, ws,
                                                 ctypes.c_void_p(s.table_host.data_ptr()), tb.value),
                        "spd_batch_table")
             with torch.cuda.stream(st):
                 s.table_dev[: tb.value].copy_(s.table_host[: tb.value], non_blocking=True)
             spd._check(self.lib.spd_batch_search(ctypes.byref(self.params), n, arr,
-                                                 ctypes.c_void_p(s.table_dev.data_ptr()),
-                                                 ctypes.c_void_p(s.ws.data_ptr()), s.ws.numel(), 0,
-                                                 ctypes.c_void_p(st.cuda_stream)), "spd_batch_search")
+                                                 ctypes.c_void_p(s.table_dev.data_ptr()), ws,
+                                                 wsb.value, 0, ctypes.c_void_p(st.cuda_stream)),
+                       "spd_batch_search")
             # counts and the first cand_prefix candidates of every window come back with the
             # batch; a window with more fetches the rest when it is retired
             pre = self.cand_prefix * spd.CANDIDATE_DTYPE.itemsize
@@ -329,9 +376,9 @@ class StreamServer:
                 for gi in range(len(groups)):
                     s.cand_host[gi, :pre].copy_(s.cand[gi, :pre], non_blocking=True)
         s.groups = groups
-        s.mem = mem
+        s.windows = windows
+        s.ws_off, s.ws_bytes = ws_off, ws_bytes
         s.busy = True
-        self.mem_in_flight += mem
         s.done.record(st)
 
     # ------------------------------------------------------------------ reporting

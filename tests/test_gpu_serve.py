@@ -153,3 +153,34 @@ def test_candidate_prefix_does_not_change_results(S):
     for a, b in zip(A, B):
         assert a.region == b.region and a.total == b.total
         assert np.array_equal(a.candidates, b.candidates)
+
+
+def test_tight_budget_same_results(S):
+    """A budget that holds about one window's workspace: batches shrink to what fits the arena,
+    the workspace in flight never exceeds the budget, and every block's candidates are those of
+    an unconstrained server."""
+    n_dm = 16
+    beams = {b: stream(b, n_dm, sizes_for(b, 6, seed=7), seed=7) for b in range(3)}
+    order = [(b, i) for i in range(6) for b in range(3)]
+    free = run(S, beams, order)
+    probe = S.StreamServer(l_end=2048, threshold=4.5, max_block=8192)
+    probe.open_beam(0, n_dm)
+    one, _ = probe._batch_plan([(n_dm, probe.cap, probe.cap)])
+    budget = one + one // 2
+    srv = S.StreamServer(l_end=2048, threshold=4.5, max_block=8192, slots=3, hbm_budget=budget)
+    for b in beams:
+        srv.open_beam(b, n_dm)
+    peak = 0
+    for b, i in order:
+        srv.submit(b, beams[b][i])
+        srv.poll()
+        peak = max(peak, srv.arena.in_use)
+    while srv.queue or any(s.busy for s in srv.slots):
+        srv.poll()
+        peak = max(peak, srv.arena.in_use)
+    assert srv.arena.size <= budget and 0 < peak <= budget
+    key = lambda r: (r.beam, r.index)
+    A, B = sorted(free.results, key=key), sorted(srv.results, key=key)
+    assert [key(r) for r in A] == [key(r) for r in B]
+    for a, b in zip(A, B):
+        assert a.region == b.region and np.array_equal(a.candidates, b.candidates)
