@@ -81,7 +81,10 @@ FAMILY = {"ig1": 1, "ig2": 2, "ig3": 3, "bd8": 4, "bd16": 5, "bd32": 6, "dit": 7
 def launch_kernel_name(method: str, info, i: int) -> str:
     """Kernel symbol of filter launch i, as rocprofv3 lists it."""
     if method == "exh":
-        return "spd::exh_kernel<true>" if info.launch_first_level[i] >= 0 else "spd::scales_kernel"
+        if info.launch_first_level[i] < 0:
+            return "spd::scales_kernel"
+        multi = "true" if int(info.segment) > 256 else "false"      # items per wave > 1
+        return f"spd::exh_kernel<true, {multi}>"
     first = "true" if info.launch_first_level[i] == 0 else "false"
     return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}, false>"
 

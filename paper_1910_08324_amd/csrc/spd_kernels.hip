@@ -534,8 +534,12 @@ __device__ __forceinline__ float load_z(const float *xr, int r, int n_in, float 
 
 // 64 widths L0 .. L0+63 at the lane's 4 starts: running sums X, group maxima gm.  The window
 // z[s0 + 4 lane + L0 - 1 ..] is read from the LDS ring one float4 per 4 widths.
+// The width scales of a row are read-only during the launch and indexed by the group's widths,
+// which every lane shares: addressed in the constant address space they load as scalar reads.
+typedef __attribute__((address_space(4))) const float *ConstFloatPtr;
+
 template <bool CHECK, bool DENSE>
-__device__ __forceinline__ void exh_group(const float4 *ring4, int jb4, int L0, const float *scale,
+__device__ __forceinline__ void exh_group(const float4 *ring4, int jb4, int L0, ConstFloatPtr scale,
                                           const uint32_t *evalmask, int Lw, const int room[4],
                                           float X[4], float gm[4]) {
     float4 wa = ring4[jb4 & 511];
@@ -565,15 +569,15 @@ __device__ __forceinline__ void exh_group(const float4 *ring4, int jb4, int L0, 
     }
 }
 
-template <bool DENSE>
+template <bool DENSE, bool MULTI>
 __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
     __shared__ float4 ring4[512];                  // 2048 floats
 
-    // A wave takes `per` consecutive work items of a row (several when every width fits one
-    // block of the ring, so each further item needs only 256 new samples, loaded while the
+    // A wave takes `per` consecutive work items of a row (MULTI: several, when every width fits
+    // one block of the ring, so each further item needs only 256 new samples, loaded while the
     // previous item computes).  Ring position 0 holds sample `base`.
     const int lane = threadIdx.x;
-    const int per = A.segs_per_wave;
+    const int per = MULTI ? A.segs_per_wave : 1;
     const int waves_per_row = (A.n_seg + per - 1) / per;
     const int d = blockIdx.x / waves_per_row;
     const int g0 = (blockIdx.x - d * waves_per_row) * per;
@@ -617,7 +621,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
     const int s0 = g * kExhSlots;
     const int ro4 = (s0 - base) >> 2;              // ring offset (float4) of this item's window
     // the next item's window reaches 256 samples further: fetch them now, store after this item
-    const bool fetch = (g + 1 < g_end) && (s0 + kExhSlots + 768 > loaded_to);
+    const bool fetch = MULTI && (g + 1 < g_end) && (s0 + kExhSlots + 768 > loaded_to);
     float4 nx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (fetch) nx = load4(loaded_to + lane * 4);
 
@@ -651,9 +655,9 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
             }
             const int jb4 = ro4 + lane + ((L0 - 1) >> 2);
             if (fast)
-                exh_group<false, DENSE>(ring4, jb4, L0, srow, A.evalmask, Lw, room, X, gm);
+                exh_group<false, DENSE>(ring4, jb4, L0, (ConstFloatPtr)srow, A.evalmask, Lw, room, X, gm);
             else
-                exh_group<true, DENSE>(ring4, jb4, L0, srow, A.evalmask, Lw, room, X, gm);
+                exh_group<true, DENSE>(ring4, jb4, L0, (ConstFloatPtr)srow, A.evalmask, Lw, room, X, gm);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 if (gm[v] > best[v]) {
@@ -1053,10 +1057,16 @@ uint64_t family_mask(int fam, int pattern) {
 int launch_exhaustive(const ExhArgs &a, bool dense, void *stream) {
     const int64_t per_row = (a.n_seg + a.segs_per_wave - 1) / a.segs_per_wave;
     const dim3 grid((unsigned)((int64_t)a.n_dm * per_row));
-    if (dense)
-        hipLaunchKernelGGL(exh_kernel<true>, grid, dim3(64), 0, (hipStream_t)stream, a);
+    const bool multi = a.segs_per_wave > 1;
+    hipStream_t st = (hipStream_t)stream;
+    if (dense && multi)
+        hipLaunchKernelGGL((exh_kernel<true, true>), grid, dim3(64), 0, st, a);
+    else if (dense)
+        hipLaunchKernelGGL((exh_kernel<true, false>), grid, dim3(64), 0, st, a);
+    else if (multi)
+        hipLaunchKernelGGL((exh_kernel<false, true>), grid, dim3(64), 0, st, a);
     else
-        hipLaunchKernelGGL(exh_kernel<false>, grid, dim3(64), 0, (hipStream_t)stream, a);
+        hipLaunchKernelGGL((exh_kernel<false, false>), grid, dim3(64), 0, st, a);
     return (int)hipGetLastError();
 }
 
