@@ -45,8 +45,11 @@ bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 // shifted decimation x^{k+1}[n] = x^k[2n + L^k_max] + x^k[2n + L^k_max + 1] needs L^k_max even.
 // Exhaustive search: 256-slot items per wave when the caller leaves it to the library.  Four
 // items amortise the window fill and keep the next item's samples in flight; measured on gfx950
-// they gain 5-20% up to L_end 256 at every shape tried, and at L_end 512 only on short rows.
-int exh_default_items(int32_t l_end, int32_t n_out) {
+// they gain 5-20% up to L_end 256, and at L_end 512 on short rows, as long as the launch still
+// has some 32 waves per compute unit (with fewer, one item per wave keeps more of them busy).
+int exh_default_items(int32_t l_end, int32_t n_dm, int32_t n_out) {
+    const int64_t waves4 = (int64_t)n_dm * ceil_div(ceil_div(n_out, spd::kExhSlots), 4);
+    if (waves4 < 8192) return 1;
     if (l_end <= 256) return 4;
     if (l_end <= 512 && n_out <= 16384) return 4;
     return 1;
@@ -327,7 +330,7 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
     if (!lossy) {
         // a wave takes 1, 2 or 4 consecutive 256-slot items; more than one only while every
         // width fits one LDS window, so that the window slides on from item to item
-        const int per = p->segment == 0 ? exh_default_items(s.l_end, n_out)
+        const int per = p->segment == 0 ? exh_default_items(s.l_end, n_dm, n_out)
                                          : p->segment / spd::kExhSlots;
         if (p->segment != 0 && (p->segment % spd::kExhSlots != 0 ||
                                 (per != 1 && per != 2 && per != spd::kExhItemsPerWave)))
