@@ -641,8 +641,9 @@ struct InferArgs {
 constexpr int ACT_LD = CH + 8;
 __device__ __forceinline__ int act_at(int pp, int c) { return pp * ACT_LD + (c << 3); }
 
-// one layer of a row held in LDS: out = relu(W in + b), 2 tiles of 32 positions per wave.  The
-// layer-1 input (8 features per position, 16 bytes) is a plain row; wider inputs are padded.
+// one layer of a row held in LDS: out = relu(W in + b), 2 tiles of 32 positions per wave, their
+// two accumulation chains interleaved so that consecutive MFMAs are independent.  The layer-1
+// input (8 features per position, 16 bytes) is a plain row; wider inputs are padded.
 template <int CI>
 __device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, const float *bias,
                                          uint16_t *out, int wave, int l) {
@@ -654,29 +655,35 @@ __device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, 
     bf16x8 wa[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) wa[s] = load8(w + n * KWC + 16 * s + 8 * h);
+    float bv[16];                                   // bias of output channel 8 g + 4 h + j
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const int p0 = wave * 64 + half * 32;
-        f32x16 acc;
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+        for (int j = 0; j < 4; ++j) bv[4 * g + j] = bias[8 * g + 4 * h + j];
+    f32x16 acc[2];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
             // k = 16 s + 8 h: tap s / 2, channels 16 (s % 2) + 8 h .. + 7 of position p0 + n + tap
+            const int p0 = wave * 64 + t * 32;
             const uint16_t *src = CI == CH ? in + act_at(p0 + n + (s >> 1), 2 * (s & 1) + h)
                                            : in + (p0 + n) * CI + 16 * s + 8 * h;
-            const bf16x8 b = load8(src);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[s], b, acc, 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[s], load8(src), acc[t], 0, 0, 0);
         }
-        const int po = p0 + n + 2;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int po = wave * 64 + t * 32 + n + 2;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             uint16_t hv[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int co = 8 * g + 4 * h + j;
-                hv[j] = to_bf16(fmaxf(acc[4 * g + j] + bias[co], 0.0f));
-            }
+            for (int j = 0; j < 4; ++j) hv[j] = to_bf16(fmaxf(acc[t][4 * g + j] + bv[4 * g + j], 0.0f));
             *reinterpret_cast<uint2 *>(out + act_at(po, g) + 4 * h) =
                 make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
                            (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
