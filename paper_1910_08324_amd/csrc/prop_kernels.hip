@@ -10,6 +10,8 @@
 // The weight gradient is the same product with positions as the reduction index.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -641,25 +643,30 @@ struct InferArgs {
 constexpr int ACT_LD = CH + 8;
 __device__ __forceinline__ int act_at(int pp, int c) { return pp * ACT_LD + (c << 3); }
 
+// The weights of one layer as this lane feeds them to the MFMA (A operand: output channel n =
+// lane % 32, k = 16 s + 8 (lane / 32) .. + 7), held in registers across the rows of a launch.
+template <int CI>
+struct LayerW {
+    static constexpr int KS = (TAPS * CI + 15) / 16;
+    bf16x8 w[KS];
+    __device__ __forceinline__ void load(const uint16_t *wg, int l) {
+        const int h = l >> 5, n = l & 31;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) w[s] = load8(wg + n * (KS * 16) + 16 * s + 8 * h);
+    }
+};
+
 // one layer of a row held in LDS: out = relu(W in + b), 2 tiles of 32 positions per wave, their
 // two accumulation chains interleaved so that consecutive MFMAs are independent.  The layer-1
-// input (8 features per position, 16 bytes) is a plain row; wider inputs are padded.
+// input (8 features per position, 16 bytes) is a plain row; wider inputs are padded.  bias: the
+// layer's 32 biases in LDS.
 template <int CI>
-__device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, const float *bias,
+__device__ __forceinline__ void conv_lds(const uint16_t *in, const LayerW<CI> &W, const float *bias,
                                          uint16_t *out, int wave, int l) {
-    constexpr int KS = (TAPS * CI + 15) / 16;
-    constexpr int KWC = KS * 16;
+    constexpr int KS = LayerW<CI>::KS;
     static_assert(CI == FCH || CI == CH, "layer inputs are the features or an activation row");
     const int h = l >> 5;
     const int n = l & 31;
-    bf16x8 wa[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) wa[s] = load8(w + n * KWC + 16 * s + 8 * h);
-    float bv[16];                                   // bias of output channel 8 g + 4 h + j
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[4 * g + j] = bias[8 * g + 4 * h + j];
     f32x16 acc[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -673,7 +680,7 @@ __device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, 
             const int p0 = wave * 64 + t * 32;
             const uint16_t *src = CI == CH ? in + act_at(p0 + n + (s >> 1), 2 * (s & 1) + h)
                                            : in + (p0 + n) * CI + 16 * s + 8 * h;
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[s], load8(src), acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(W.w[s], load8(src), acc[t], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -681,9 +688,11 @@ __device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, 
         const int po = wave * 64 + t * 32 + n + 2;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
+            const float4 bv = *reinterpret_cast<const float4 *>(bias + 8 * g + 4 * h);
+            const float bb[4] = {bv.x, bv.y, bv.z, bv.w};
             uint16_t hv[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) hv[j] = to_bf16(fmaxf(acc[t][4 * g + j] + bv[4 * g + j], 0.0f));
+            for (int j = 0; j < 4; ++j) hv[j] = to_bf16(fmaxf(acc[t][4 * g + j] + bb[j], 0.0f));
             *reinterpret_cast<uint2 *>(out + act_at(po, g) + 4 * h) =
                 make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
                            (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
@@ -691,55 +700,81 @@ __device__ __forceinline__ void conv_lds(const uint16_t *in, const uint16_t *w, 
     }
 }
 
+// Persistent: each work-group takes rows blockIdx.x, + gridDim.x, ... with the weights in
+// registers for the whole launch, and fetches the next row's features while it computes the
+// current one.
 __global__ __launch_bounds__(256) void infer_kernel(const InferArgs A) {
+    constexpr int NF = RP * FCH / 8;                 // 16-byte pieces of a row's features
+    static_assert(NF > 256 && NF <= 512, "a row's features take one or two pieces per thread");
     __shared__ __attribute__((aligned(16))) uint16_t f[RP * FCH];
     __shared__ __attribute__((aligned(16))) uint16_t a[RP * ACT_LD];
     __shared__ __attribute__((aligned(16))) uint16_t b[RP * ACT_LD];
+    __shared__ __attribute__((aligned(16))) float bias[3 * CH];
     __shared__ float red[8];
-    const int r = blockIdx.x;
-    if (r >= A.rows) return;
+    if ((int)blockIdx.x >= A.rows) return;
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int l = tid & 63;
-    const uint16_t *fr = A.feat + (int64_t)r * RP * FCH;
-    for (int i = tid; i < RP * FCH / 8; i += 256)
-        reinterpret_cast<uint4 *>(f)[i] = reinterpret_cast<const uint4 *>(fr)[i];
-    // zero pads of the activation buffers (positions 0, 1, 258 .. 261)
+    LayerW<FCH> W1;
+    LayerW<CH> W2, W3;
+    W1.load(A.wb.w1, l);
+    W2.load(A.wb.w2, l);
+    W3.load(A.wb.w3, l);
+    if (tid < 3 * CH) {
+        const int j = tid / CH, c = tid - j * CH;
+        const int off = j == 0 ? SPD_PROP_OFF_B1 : (j == 1 ? SPD_PROP_OFF_B2 : SPD_PROP_OFF_B3);
+        bias[tid] = A.params[off + c];
+    }
+    // zero pads of the activation buffers (positions 0, 1, 258 .. 261); the layers never write them
     for (int i = tid; i < 6 * CH / 8; i += 256) {
         const int pos = i / (CH / 8), part = i - pos * (CH / 8);
         const int pp = pos < 2 ? pos : POS + pos;
         *reinterpret_cast<uint4 *>(a + act_at(pp, part)) = make_uint4(0u, 0u, 0u, 0u);
         *reinterpret_cast<uint4 *>(b + act_at(pp, part)) = make_uint4(0u, 0u, 0u, 0u);
     }
-    __syncthreads();
-    conv_lds<FCH>(f, A.wb.w1, A.params + SPD_PROP_OFF_B1, a, wave, l);
-    __syncthreads();
-    conv_lds<CH>(a, A.wb.w2, A.params + SPD_PROP_OFF_B2, b, wave, l);
-    __syncthreads();
-    conv_lds<CH>(b, A.wb.w3, A.params + SPD_PROP_OFF_B3, a, wave, l);
-    __syncthreads();
-    // read-out of position tid, then the row's max and sum of exp(s - max)
-    float act[CH];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(a + act_at(tid + 2, q));
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            act[8 * q + 2 * e] = __uint_as_float(w[e] << 16);
-            act[8 * q + 2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
-        }
-    }
     const float *wh = A.params + SPD_PROP_OFF_WH;
-    float sv = 0.0f;
+    const float bh = A.params[SPD_PROP_OFF_BH];
+    uint4 fp0 = make_uint4(0u, 0u, 0u, 0u), fp1 = fp0;
+    auto fetch = [&](int r) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.feat + (int64_t)r * RP * FCH);
+        fp0 = src[tid];
+        if (tid + 256 < NF) fp1 = src[tid + 256];
+    };
+    fetch(blockIdx.x);
+    for (int r = blockIdx.x; r < A.rows; r += gridDim.x) {
+        reinterpret_cast<uint4 *>(f)[tid] = fp0;
+        if (tid + 256 < NF) reinterpret_cast<uint4 *>(f)[tid + 256] = fp1;
+        __syncthreads();
+        if (r + (int)gridDim.x < A.rows) fetch(r + gridDim.x);
+        conv_lds<FCH>(f, W1, bias, a, wave, l);
+        __syncthreads();
+        conv_lds<CH>(a, W2, bias + CH, b, wave, l);
+        __syncthreads();
+        conv_lds<CH>(b, W3, bias + 2 * CH, a, wave, l);
+        __syncthreads();
+        // read-out of position tid, then the row's max and sum of exp(s - max)
+        float act[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) sv += wh[c] * act[c];
-    sv += A.params[SPD_PROP_OFF_BH];
-    const float mx = block_max(sv, red);
-    const float se = block_sum(expf(sv - mx), red + 4);
-    if (tid == 0) {
-        A.row_max[r] = mx;
-        A.row_sum[r] = se;
+        for (int q = 0; q < 4; ++q) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(a + act_at(tid + 2, q));
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                act[8 * q + 2 * e] = __uint_as_float(w[e] << 16);
+                act[8 * q + 2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
+            }
+        }
+        float sv = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) sv += wh[c] * act[c];
+        sv += bh;
+        const float mx = block_max(sv, red);
+        const float se = block_sum(expf(sv - mx), red + 4);
+        if (tid == 0) {
+            A.row_max[r] = mx;
+            A.row_sum[r] = se;
+        }
+        __syncthreads();                    // f and a are rewritten for the next row
     }
 }
 
@@ -926,7 +961,14 @@ int spd_prop_forward(const float *params, const uint16_t *feat, int32_t n_tiles,
     a.row_max = B.s;
     a.row_sum = B.s + rows;
     a.rows = rows;
-    SPDP_LAUNCH(infer_kernel, dim3(rows), dim3(256), 0, s, a);
+    // persistent grid: as many work-groups as the device keeps resident at once, at most one per row
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, infer_kernel, 256, 0) != hipSuccess)
+        return fail(hipGetLastError());
+    const int grid = std::max(1, std::min(rows, cus * std::max(1, per_cu)));
+    SPDP_LAUNCH(infer_kernel, dim3(grid), dim3(256), 0, s, a);
     SPDP_LAUNCH(infer_combine_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0, s, a.row_max,
                 a.row_sum, n_tiles, logits);
     return SPD_OK;

@@ -106,10 +106,11 @@ def test_forward_matches_oracle(P):
     assert np.allclose(lg, ref, rtol=1e-4, atol=1e-4)
 
 
-def test_fused_inference_matches_training_forward(P):
+@pytest.mark.parametrize("tiles", [5, 40])
+def test_fused_inference_matches_training_forward(P, tiles):
     """spd_prop_forward keeps a row's three layers in LDS; its logits equal those of the
-    training forward pass (activations through HBM) up to the order of the final sums."""
-    tiles = 5
+    training forward pass (activations through HBM) up to the order of the final sums.  With 40
+    tiles (2560 rows) every work-group of the persistent grid takes several rows."""
     _, feat = make_batch(P, tiles, seed=41)
     net = oracle_net(41)
     N = P.Network(packed(P, net), max_tiles=tiles)
