@@ -525,27 +525,38 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel_bat
 // kept.  The winning width inside the winning group is recovered at the end by replaying that
 // group's 64 steps with the same FP32 operations, so it is the smallest width attaining the
 // maximum, exactly as a per-width argmax would give.
-// The input window z[s0 .. s0 + 256 + L_end) streams through a 2048-float LDS ring, 512 new
-// samples per block of 512 widths.
+// The input window z[s0 .. s0 + 256 + L_end) streams through a 1024-float LDS ring, 512 new
+// samples per block of 512 widths.  The ring's first 16 float4 are mirrored after its end, so a
+// group reads its 17 consecutive float4 at immediate offsets from one base address.
 // ----------------------------------------------------------------------------------------
 __device__ __forceinline__ float load_z(const float *xr, int r, int n_in, float mu, float inv) {
     return r < n_in ? (xr[r] - mu) * inv : 0.0f;
 }
 
-// 64 widths L0 .. L0+63 at the lane's 4 starts: running sums X, group maxima gm.  The window
-// z[s0 + 4 lane + L0 - 1 ..] is read from the LDS ring one float4 per 4 widths.
 // The width scales of a row are read-only during the launch and indexed by the group's widths,
 // which every lane shares: addressed in the constant address space they load as scalar reads.
 typedef __attribute__((address_space(4))) const float *ConstFloatPtr;
 
+constexpr int kRing4 = 256;        // float4 slots of the ring (1024 samples)
+constexpr int kGuard4 = 16;        // mirrored slots after the ring's end
+
+__device__ __forceinline__ void ring_put(float4 *ring4, int i, float4 v) {   // 0 <= i < kRing4
+    ring4[i] = v;
+    if (i < kGuard4) ring4[kRing4 + i] = v;
+}
+
+// 64 widths L0 .. L0+63 at the lane's 4 starts: running sums X, group maxima gm.  The window
+// z[s0 + 4 lane + L0 - 1 ..] is read from the LDS ring one float4 per 4 widths.
 template <bool CHECK, bool DENSE>
 __device__ __forceinline__ void exh_group(const float4 *ring4, int jb4, int L0, ConstFloatPtr scale,
                                           const uint32_t *evalmask, int Lw, const int room[4],
                                           float X[4], float gm[4]) {
-    float4 wa = ring4[jb4 & 511];
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f *win = reinterpret_cast<const v4f *>(ring4 + (jb4 & (kRing4 - 1)));
+    v4f wa = win[0];
 #pragma unroll 4
     for (int t = 0; t < kExhGroup / 4; ++t) {
-        const float4 wb = ring4[(jb4 + t + 1) & 511];
+        const v4f wb = win[t + 1];
         const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
         const int L = L0 + 4 * t;
 #pragma unroll
@@ -571,7 +582,7 @@ __device__ __forceinline__ void exh_group(const float4 *ring4, int jb4, int L0, 
 
 template <bool DENSE, bool MULTI>
 __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
-    __shared__ float4 ring4[512];                  // 2048 floats
+    __shared__ float4 ring4[kRing4 + kGuard4];
 
     // A wave takes `per` consecutive work items of a row (MULTI: several, when every width fits
     // one block of the ring, so each further item needs only 256 new samples, loaded while the
@@ -611,7 +622,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int j = q * 256 + lane * 4;
-        ring4[j >> 2] = load4(base + j);
+        ring_put(ring4, j >> 2, load4(base + j));
     }
     int loaded_to = base + 1024;
     __syncthreads();
@@ -669,8 +680,8 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
         }
         if (refill) {
             __syncthreads();
-            ring4[((jn >> 2) + lane) & 511] = pf0;
-            ring4[((jn >> 2) + 64 + lane) & 511] = pf1;
+            ring_put(ring4, ((jn >> 2) + lane) & (kRing4 - 1), pf0);
+            ring_put(ring4, ((jn >> 2) + 64 + lane) & (kRing4 - 1), pf1);
             __syncthreads();
         }
     }
@@ -689,7 +700,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
         for (int t = 0; t < kExhGroup; ++t) {
             const int L = Lb + t;
             if (L > Lw) break;
-            Xr += (nblk == 1) ? ring[(4 * ro4 + 4 * lane + v + L - 1) & 2047]
+            Xr += (nblk == 1) ? ring[(4 * ro4 + 4 * lane + v + L - 1) & (4 * kRing4 - 1)]
                               : load_z(xr, sv + L - 1, n_in, mu, inv);
             float snr = Xr * srow[L - 1];
             bool ok = L <= room[v];
@@ -758,7 +769,7 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
         if (lane == 0) A.slab_cnt[(int64_t)d * A.n_seg + g] = total;
     }
     if (fetch) {
-        ring4[(((loaded_to - base) >> 2) + lane) & 511] = nx;
+        ring_put(ring4, (((loaded_to - base) >> 2) + lane) & (kRing4 - 1), nx);
         loaded_to += 256;
     }
     __syncthreads();
