@@ -1,7 +1,9 @@
 """GPU parity at the full SKA-MID-like beam size (4,096 DM trials x 262,144 samples, L_end 8192,
-500 Gaussian pulses), in the launch configuration the benchmark times: plane values sampled
-across all levels and around every pulse are checked against the oracle's point evaluation, and
-candidates are checked on windows around pulses against the oracle's planes of those windows."""
+500 Gaussian pulses), in the launch configuration the benchmark times (the autotuner's tile
+length and levels per launch for the lossy methods, the library's default for the exhaustive
+search): plane values sampled across all levels and around every pulse are checked against the
+oracle's point evaluation, and candidates are checked on windows around pulses against the
+oracle's planes of those windows."""
 import sys
 import time
 
@@ -54,8 +56,14 @@ def gather(res, lev_idx, rows, slots):
 def test_ska_beam_sampled_parity(beam, method):
     from paper_1910_08324_amd import spd
     w, x, xd, mu, sg = beam
-    say(f"[full size] {method}")
     cfg = spd.Config(method, w.l_end, threshold=w.threshold)
+    if method != "exh":
+        # the launch shape the benchmark times: the autotuner's choice for this beam shape
+        from paper_1910_08324_amd import autotune
+        c = autotune.Tuner(rows=w.n_dm, reps=1).choose(method, w.l_end, w.n)
+        cfg = spd.Config(method, w.l_end, threshold=w.threshold, segment=c.segment,
+                         step_levels=c.step_levels)
+    say(f"[full size] {method} segment {cfg.segment} step_levels {cfg.step_levels}")
     mu_d = torch.from_numpy(mu).to(xd.device)
     sg_d = torch.from_numpy(sg).to(xd.device)
     t = time.time()
