@@ -35,13 +35,17 @@ int spd_msd_workspace(int32_t n_dm, int32_t n_in, int32_t levels, int64_t *bytes
 
 /*
  * spd_msd: x [n_dm][ld] float (ld >= n_in); levels 1..SPD_MAX_LEVELS with n_in >> (levels-1)
- * >= 2; tau > 0; max_iter >= 0.  Outputs (device, float): mean[n_dm], sigma[n_dm] (level 0,
- * ready for spd_search), and, if not NULL, rho[n_dm][levels] and level_sd[n_dm][levels].
- * One work-group per row; asynchronous on the stream.
+ * >= 2; tau > 0; max_iter >= 0.  Outputs (device): mean[n_dm], sigma[n_dm] (float, level 0,
+ * ready for spd_search), and, if not NULL, rho[n_dm][levels] and level_sd[n_dm][levels] (float)
+ * and passes[n_dm] (int32: estimate passes over the row, 1 + the most rejection passes any level
+ * took, at most 1 + max_iter; each pass reads the row's samples once).  The workspace holds the
+ * decimated values of levels 9 and up (fewer than n_in / 256 per row).  One work-group per row;
+ * asynchronous on the stream.  SPD_EINVAL for bad sizes or NULL mean / sigma, SPD_EWORKSPACE /
+ * SPD_EALIGN for a short or unaligned (256-byte) workspace, SPD_EHIP for a failed launch.
  */
 int spd_msd(const float *x, int64_t ld, int32_t n_dm, int32_t n_in, int32_t levels, float tau,
             int32_t max_iter, float *mean, float *sigma, float *rho, float *level_sd,
-            void *workspace, int64_t workspace_bytes, void *hip_stream);
+            int32_t *passes, void *workspace, int64_t workspace_bytes, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -39,19 +39,23 @@ def mean_sd(v) -> tuple:
     return m, sd
 
 
-def robust_mean_sd(v, tau: float, max_iter: int) -> tuple:
-    """(mean, sd, kept) with iterative rejection of |v - mean| > tau sd."""
+def robust_mean_sd(v, tau: float, max_iter: int, with_passes: bool = False) -> tuple:
+    """(mean, sd, kept) with iterative rejection of |v - mean| > tau sd; with_passes adds the
+    number of passes over the values (the first estimate plus every rejection pass, including
+    the one that finds the kept set unchanged)."""
     v = np.asarray(v, np.float64)
     m, sd = mean_sd(v)
     kept = v.size
+    passes = 1
     for _ in range(max_iter):
         keep = np.abs(v - m) <= tau * sd
+        passes += 1
         k = int(keep.sum())
         if k == kept or k < 2:
             break
         kept = k
         m, sd = mean_sd(v[keep])
-    return m, sd, kept
+    return (m, sd, kept, passes) if with_passes else (m, sd, kept)
 
 
 def decimate(x, k: int) -> np.ndarray:
@@ -62,18 +66,20 @@ def decimate(x, k: int) -> np.ndarray:
 
 def msd_row(x, levels: int, tau: float = 2.0, max_iter: int = 10) -> dict:
     """Mean, sd and per-level sd / rho of one row; levels = K + 1 decimation levels 0..K."""
-    out = {"mean": [], "sd": [], "kept": []}
+    out = {"mean": [], "sd": [], "kept": [], "passes": []}
     for k in range(levels):
         y = decimate(x, k)
         if y.size < 2:
             out["mean"].append(float("nan"))
             out["sd"].append(float("nan"))
             out["kept"].append(int(y.size))
+            out["passes"].append(0)
             continue
-        m, sd, kept = robust_mean_sd(y, tau, max_iter)
+        m, sd, kept, passes = robust_mean_sd(y, tau, max_iter, with_passes=True)
         out["mean"].append(m)
         out["sd"].append(sd)
         out["kept"].append(kept)
+        out["passes"].append(passes)
     sd0 = out["sd"][0]
     out["rho"] = [s / (math.sqrt(2.0 ** k) * sd0) for k, s in enumerate(out["sd"])]
     return out

@@ -1,8 +1,17 @@
 // Noise statistics per DM trial (declared in include/spd_msd.h): robust mean and standard
 // deviation with iterative outlier rejection, for the samples and for every power-of-two
-// decimation of them.  One work-group per row, FP64 throughout.  Partial statistics
-// (count, mean, sum of squared deviations) are accumulated per thread with single-value updates
-// and merged pairwise with Chan, Golub & LeVeque's formula, in a fixed order.
+// decimation of them.  One work-group per row, FP64 throughout.
+//
+// A pass reads the row once and serves every level at the same time.  The row streams through
+// in tiles of 1024 samples, one float4 per thread; inside a tile the decimated values of levels
+// 1..8 are formed in registers (levels 1, 2 within a thread, 3..8 by pairwise sums across lanes)
+// and each lane accumulates the values it holds.  Values of levels 9 and up (at most 1/256 of the
+// samples) are formed once, in the first pass, into the workspace, and later passes read them
+// from there.  Per level, each thread keeps a count and the sums of (value - shift) and of its
+// square, with the shift the level's current mean estimate; after the pass the threads' partial
+// statistics (count, mean, sum of squared deviations) are merged pairwise with Chan, Golub &
+// LeVeque's formula in a fixed order.  Levels converge independently; the row's passes stop
+// when every level has.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -14,6 +23,9 @@
 namespace spdm {
 
 constexpr int kThreads = 256;
+constexpr int kTile = 4 * kThreads;   // samples per tile
+constexpr int kRegLevels = 9;          // levels 0..8 formed in registers
+constexpr int kWsFirst = 9;            // levels 9.. live in the workspace
 
 struct Part {
     double n, mean, m2;
@@ -31,13 +43,6 @@ __device__ __forceinline__ Part merge(Part a, Part b) {
     return r;
 }
 
-__device__ __forceinline__ void add(Part &p, double v) {
-    p.n += 1.0;
-    const double d = v - p.mean;
-    p.mean += d / p.n;
-    p.m2 += d * (v - p.mean);
-}
-
 // merge the 256 threads' partials: butterflies inside each wave, then the four waves in order
 __device__ Part block_merge(Part p, Part *sh) {
     for (int o = 1; o < 64; o <<= 1) {
@@ -52,77 +57,260 @@ __device__ Part block_merge(Part p, Part *sh) {
     __syncthreads();
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = p;
     __syncthreads();
-    Part r = merge(merge(sh[0], sh[1]), merge(sh[2], sh[3]));
-    return r;
+    return merge(merge(sh[0], sh[1]), merge(sh[2], sh[3]));
 }
+
+// a thread's running sums of one level: count, sum and sum of squares of (value - shift)
+struct Acc {
+    int n;
+    double s1, s2;
+};
+
+__device__ __forceinline__ void acc_reset(Acc &a) {
+    a.n = 0;
+    a.s1 = a.s2 = 0.0;
+}
+
+__device__ __forceinline__ Part acc_part(const Acc &a, double shift) {
+    Part p = {0.0, 0.0, 0.0};
+    if (a.n > 0) {
+        p.n = (double)a.n;
+        p.mean = shift + a.s1 / p.n;
+        p.m2 = fmax(0.0, a.s2 - a.s1 * (a.s1 / p.n));
+    }
+    return p;
+}
+
+// the estimate of one level, shared by the work-group
+struct Level {
+    double shift;       // subtracted before summing
+    double m, lim;      // a value is kept in a rejection pass if |value - m| <= lim
+    double sd, kept;
+    int active;         // still being refined
+    int iters;          // rejection passes that changed the estimate
+};
 
 struct MsdArgs {
     const float *x;
     int64_t ld;
-    double *ws;          // per row: level k >= 1 series at offset n_in - (n_in >> (k - 1)) ...
+    double *ws;          // per row: the values of levels 9.. (n >> 9 of level 9, then level 10, ...)
     int64_t ws_row;      // doubles per row
     float *mean, *sigma, *rho, *level_sd;
+    int32_t *passes;
     int32_t n_dm, n_in, levels, max_iter;
     double tau;
 };
 
-// value i of the level's series: level 0 reads the samples, later levels the workspace
-__device__ __forceinline__ double value(const float *xr, const double *yk, int k, int64_t i) {
-    return k == 0 ? (double)xr[i] : yk[i];
+// take value v of a level (valid or not) into the thread's sums.  After the first pass the
+// shift is the level's mean, so one difference serves the test and the sums.
+__device__ __forceinline__ void take(Acc &a, const Level &L, bool first, bool valid, double v) {
+    const double d = v - L.shift;
+    const bool ok = valid && (first || fabs(d) <= L.lim);
+    const double e = ok ? d : 0.0;           // (d may be NaN for a value past the data)
+    a.n += ok ? 1 : 0;
+    a.s1 += e;
+    a.s2 = fma(e, e, a.s2);
 }
 
 __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
     __shared__ Part sh[4];
+    __shared__ Level lv[SPD_MAX_LEVELS];
+    __shared__ double t8[4];                   // level-8 value of each wave in the current tile
+    __shared__ double slot_buf[4][64];         // per wave: this tile's level 3..8 values
+    __shared__ int any_active;
     const int d = blockIdx.x;
     if (d >= A.n_dm) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int n = A.n_in;
+    const int K = A.levels;
+    const int kreg = min(K, kRegLevels);
     const float *xr = A.x + (int64_t)d * A.ld;
     double *wr = A.ws + (int64_t)d * A.ws_row;
-    double sd0 = 0.0;
-    int64_t off = 0;                 // workspace offset of the current level's series
-    const double *prev = nullptr;    // previous level's series (level >= 2)
-    for (int k = 0; k < A.levels; ++k) {
-        const int64_t n = (int64_t)A.n_in >> k;
-        double *yk = wr + off;
-        if (k >= 1) {
-            for (int64_t i = threadIdx.x; i < n; i += kThreads)
-                yk[i] = (k == 1) ? (double)xr[2 * i] + (double)xr[2 * i + 1]
-                                 : prev[2 * i] + prev[2 * i + 1];
+    const int n_tiles = (n + kTile - 1) / kTile;
+    const bool vec = (((uintptr_t)xr) & 15) == 0;
+    // a tile gives each wave 32 + 16 + 8 + 4 + 2 + 1 values of levels 3..8: lanes 0..31 take
+    // level 3, 32..47 level 4, 48..55 level 5, 56..59 level 6, 60..61 level 7, 62 level 8
+    constexpr int kSlot[kRegLevels] = {0, 0, 0, 0, 32, 48, 56, 60, 62};
+    const int my_k = lane < 32 ? 3 : lane < 48 ? 4 : lane < 56 ? 5 : lane < 60 ? 6 : lane < 62 ? 7
+                                                                                   : lane < 63 ? 8 : kRegLevels;
+    double *slots = slot_buf[wave];
+    slots[63] = __builtin_nan("");               // lane 63 has no value
+
+    if (tid < K) {
+        Level &L = lv[tid];
+        L.shift = (double)xr[0] * (double)(1 << tid);   // first pass: a value of the right size
+        L.m = 0.0;
+        L.lim = 0.0;
+        L.sd = 0.0;
+        L.kept = 0.0;
+        L.active = 1;
+        L.iters = 0;
+    }
+    __syncthreads();
+
+    int pass = 0;
+    for (; pass <= A.max_iter; ++pass) {
+        const bool first = pass == 0;
+        if (!first) {
+            if (tid == 0) {
+                int a = 0;
+                for (int k = 0; k < K; ++k) a |= lv[k].active;
+                any_active = a;
+            }
             __syncthreads();
+            if (!any_active) break;
         }
-        // first estimate over every value, then passes with rejection
-        Part p = {0.0, 0.0, 0.0};
-        for (int64_t i = threadIdx.x; i < n; i += kThreads) add(p, value(xr, yk, k, i));
-        Part t = block_merge(p, sh);
-        double m = t.mean;
-        double sd = t.n > 1.0 ? sqrt(t.m2 / (t.n - 1.0)) : 0.0;
-        double kept = t.n;
-        for (int it = 0; it < A.max_iter; ++it) {
-            const double lim = A.tau * sd;
-            Part q = {0.0, 0.0, 0.0};
-            for (int64_t i = threadIdx.x; i < n; i += kThreads) {
-                const double v = value(xr, yk, k, i);
-                if (fabs(v - m) <= lim) add(q, v);
+        // the samples are read again only while a level formed from them in registers is open
+        // (levels 9.. come from the workspace after the first pass)
+        bool read_row = first;
+        for (int k = 0; k < kreg; ++k) read_row = read_row || lv[k].active;
+        Acc a0, a1, a2, am;                      // levels 0, 1, 2 and this lane's level of 3..8
+        acc_reset(a0);
+        acc_reset(a1);
+        acc_reset(a2);
+        acc_reset(am);
+        const Level L0 = lv[0];
+        const Level L1 = lv[min(1, K - 1)];
+        const Level L2 = lv[min(2, K - 1)];
+        const Level Lm = lv[min(my_k, K - 1)];
+        const bool on0 = first || L0.active;
+        const bool on1 = K > 1 && (first || L1.active);
+        const bool on2 = K > 2 && (first || L2.active);
+        const bool onm = my_k < kreg && (first || Lm.active);
+
+        auto fetch = [&](int tile, float4 &f) {
+            const int s = tile * kTile + 4 * tid;
+            if (vec && s + 3 < n) {
+                f = *reinterpret_cast<const float4 *>(xr + s);
+            } else {
+                f.x = s + 0 < n ? xr[s + 0] : 0.0f;
+                f.y = s + 1 < n ? xr[s + 1] : 0.0f;
+                f.z = s + 2 < n ? xr[s + 2] : 0.0f;
+                f.w = s + 3 < n ? xr[s + 3] : 0.0f;
             }
-            const Part u = block_merge(q, sh);
-            if (u.n == kept || u.n < 2.0) break;
-            kept = u.n;
-            m = u.mean;
-            sd = sqrt(u.m2 / (u.n - 1.0));
-        }
-        if (k == 0) sd0 = sd;
-        if (threadIdx.x == 0) {
-            if (k == 0) {
-                A.mean[d] = (float)m;
-                A.sigma[d] = (float)sd;
+        };
+        float4 nxt = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (read_row) fetch(0, nxt);
+        for (int tile = 0; read_row && tile < n_tiles; ++tile) {
+            const float4 cur = nxt;
+            if (tile + 1 < n_tiles) fetch(tile + 1, nxt);        // in flight while this tile computes
+            const int s = tile * kTile + 4 * tid;                // first sample of this thread
+            const double v0[4] = {(double)cur.x, (double)cur.y, (double)cur.z, (double)cur.w};
+            if (on0)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) take(a0, L0, first, s + q < n, v0[q]);
+            // levels 1, 2 within the thread
+            const double v1a = v0[0] + v0[1], v1b = v0[2] + v0[3];
+            if (on1) {
+                take(a1, L1, first, s + 2 <= n, v1a);
+                take(a1, L1, first, s + 4 <= n, v1b);
             }
-            if (A.rho) A.rho[(int64_t)d * A.levels + k] = (float)(sd / (sqrt((double)(1 << k)) * sd0));
-            if (A.level_sd) A.level_sd[(int64_t)d * A.levels + k] = (float)sd;
+            double v = v1a + v1b;
+            if (on2) take(a2, L2, first, s + 4 <= n, v);
+            // levels 3..8 across lanes: after step k, lane l holds the value of level k that starts
+            // at its own samples when l is a multiple of 2^(k-2); holders park their values in the
+            // wave's 64 slots (level k at slots kSlot[k] .., one per holder, NaN past the data), and
+            // every lane then takes the one value of its own level in its slot
+#pragma unroll
+            for (int k = 3; k < kRegLevels; ++k) {
+                const int span = 1 << (k - 3);
+                v = v + __shfl_down(v, span);
+                if ((lane & ((span << 1) - 1)) == 0)
+                    slots[kSlot[k] + (lane >> (k - 2))] = s + (1 << k) <= n ? v : __builtin_nan("");
+            }
+            if (onm) {
+                const double mv = slots[lane];                   // written by this wave above
+                take(am, Lm, first, !__builtin_isnan(mv), mv);
+            }
+            // levels 9 and 10 (and the level-10 values the higher levels are built from): the
+            // first pass writes them to the workspace
+            if (first && K > kWsFirst) {
+                if (lane == 0) t8[wave] = v;
+                __syncthreads();
+                if (tid == 0) {
+                    const int64_t i9 = (int64_t)tile * 2;
+                    const double a9 = t8[0] + t8[1], b9 = t8[2] + t8[3];
+                    const int64_t n9 = n >> 9;
+                    if (i9 < n9) wr[i9] = a9;
+                    if (i9 + 1 < n9) wr[i9 + 1] = b9;
+                    if (K > 10 && tile < (n >> 10)) wr[n9 + tile] = a9 + b9;
+                }
+                __syncthreads();
+            }
         }
-        if (k >= 1) {
-            prev = yk;
-            off += n;
+        if (first && K > 11) {
+            // levels 11.. from pairs of the level below, all in the workspace
+            int64_t off_prev = (int64_t)(n >> 9), off = off_prev + (n >> 10);
+            for (int k = 11; k < K; ++k) {
+                const int64_t cnt = (int64_t)(n >> k);
+                for (int64_t i = tid; i < cnt; i += kThreads) wr[off + i] = wr[off_prev + 2 * i] + wr[off_prev + 2 * i + 1];
+                off_prev = off;
+                off += cnt;
+                __syncthreads();
+            }
         }
-        __syncthreads();
+
+        // merge the pass's statistics and update every level still being refined (the decision
+        // to skip a level is uniform across the work-group)
+        auto update = [&](int k, Part p) {
+            const Part u = block_merge(p, sh);
+            if (tid == 0) {
+                Level &S = lv[k];
+                if (first) {
+                    S.m = u.mean;
+                    S.sd = u.n > 1.0 ? sqrt(u.m2 / (u.n - 1.0)) : 0.0;
+                    S.kept = u.n;
+                    S.active = A.max_iter > 0;
+                } else if (u.n == S.kept || u.n < 2.0) {
+                    S.active = 0;
+                } else {
+                    S.kept = u.n;
+                    S.m = u.mean;
+                    S.sd = sqrt(u.m2 / (u.n - 1.0));
+                    S.iters += 1;
+                    if (S.iters >= A.max_iter) S.active = 0;
+                }
+                S.lim = A.tau * S.sd;
+                S.shift = S.m;
+            }
+            __syncthreads();
+        };
+        if (K > 0 && (first || lv[0].active)) update(0, acc_part(a0, lv[0].shift));
+        if (K > 1 && (first || lv[1].active)) update(1, acc_part(a1, lv[1].shift));
+        if (K > 2 && (first || lv[2].active)) update(2, acc_part(a2, lv[2].shift));
+        for (int k = 3; k < kreg; ++k) {
+            if (first || lv[k].active) {
+                Part p = {0.0, 0.0, 0.0};
+                if (my_k == k) p = acc_part(am, lv[k].shift);
+                update(k, p);
+            }
+        }
+        int64_t off = 0;
+        for (int k = kWsFirst; k < K; ++k) {
+            const int64_t cnt = (int64_t)(n >> k);
+            const Level Lk = lv[k];
+            if (first || Lk.active) {
+                Acc a;
+                acc_reset(a);
+                for (int64_t i = tid; i < cnt; i += kThreads) take(a, Lk, first, true, wr[off + i]);
+                update(k, acc_part(a, Lk.shift));
+            }
+            off += cnt;
+        }
+    }
+
+    if (tid < K) {
+        const double sd0 = lv[0].sd;
+        const double sd = lv[tid].sd;
+        if (tid == 0) {
+            A.mean[d] = (float)lv[0].m;
+            A.sigma[d] = (float)sd0;
+            if (A.passes) A.passes[d] = pass;
+        }
+        if (A.rho) A.rho[(int64_t)d * K + tid] = (float)(sd / (sqrt((double)(1 << tid)) * sd0));
+        if (A.level_sd) A.level_sd[(int64_t)d * K + tid] = (float)sd;
     }
 }
 
@@ -131,16 +319,17 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
 extern "C" {
 
 int spd_msd_workspace(int32_t n_dm, int32_t n_in, int32_t levels, int64_t *bytes) {
-    if (!bytes || n_dm < 1 || n_in < 2 || levels < 1 || levels > SPD_MAX_LEVELS ||
-        ((int64_t)n_in >> (levels - 1)) < 2)
+    if (!bytes || n_dm < 1 || n_in < 2 || n_in > INT32_MAX - 4096 || levels < 1 ||
+        levels > SPD_MAX_LEVELS || ((int64_t)n_in >> (levels - 1)) < 2)
         return SPD_EINVAL;
-    *bytes = (int64_t)n_dm * n_in * 8 + 256;   // levels 1.. need fewer than n_in doubles per row
+    // levels 9.. of every row: fewer than n_in / 256 values
+    *bytes = (int64_t)n_dm * ((n_in >> 8) + 8) * 8 + 256;
     return SPD_OK;
 }
 
 int spd_msd(const float *x, int64_t ld, int32_t n_dm, int32_t n_in, int32_t levels, float tau,
             int32_t max_iter, float *mean, float *sigma, float *rho, float *level_sd,
-            void *workspace, int64_t workspace_bytes, void *hip_stream) {
+            int32_t *passes, void *workspace, int64_t workspace_bytes, void *hip_stream) {
     int64_t need = 0;
     const int st = spd_msd_workspace(n_dm, n_in, levels, &need);
     if (st != SPD_OK) return st;
@@ -151,11 +340,12 @@ int spd_msd(const float *x, int64_t ld, int32_t n_dm, int32_t n_in, int32_t leve
     a.x = x;
     a.ld = ld;
     a.ws = static_cast<double *>(workspace);
-    a.ws_row = n_in;
+    a.ws_row = (n_in >> 8) + 8;
     a.mean = mean;
     a.sigma = sigma;
     a.rho = rho;
     a.level_sd = level_sd;
+    a.passes = passes;
     a.n_dm = n_dm;
     a.n_in = n_in;
     a.levels = levels;

@@ -40,14 +40,19 @@ def rows_with_structure(n, seed):
     return np.stack(out).astype(np.float32)
 
 
-@pytest.mark.parametrize("tau,max_iter", [(2.0, 10), (3.0, 0), (2.5, 3)])
-def test_msd_matches_oracle(M, tau, max_iter):
-    n, levels = 100003, 9
+@pytest.mark.parametrize("n,levels,tau,max_iter", [(100003, 9, 2.0, 10), (100003, 16, 3.0, 0),
+                                                   (100003, 16, 2.5, 3), (700, 9, 2.0, 10),
+                                                   (262144, 18, 3.0, 10), (5000, 11, 2.0, 10)])
+def test_msd_matches_oracle(M, n, levels, tau, max_iter):
+    """Levels 0..8 are formed in registers and levels 9.. in the workspace; rows that are not a
+    whole number of 1024-sample tiles, shorter than one tile, and up to the longest level."""
     x = rows_with_structure(n, 1)
-    mean, sigma, rho, lsd = M.msd(torch.from_numpy(x).cuda(), levels, tau=tau, max_iter=max_iter)
-    mean, sigma, rho, lsd = (t.cpu().numpy() for t in (mean, sigma, rho, lsd))
+    mean, sigma, rho, lsd, passes = M.msd(torch.from_numpy(x).cuda(), levels, tau=tau,
+                                          max_iter=max_iter, with_passes=True)
+    mean, sigma, rho, lsd, passes = (t.cpu().numpy() for t in (mean, sigma, rho, lsd, passes))
     for d in range(x.shape[0]):
         r = om.msd_row(x[d], levels, tau=tau, max_iter=max_iter)
+        assert passes[d] == max(r["passes"]), d
         # FP64 on both sides, rounded once to FP32 here
         assert mean[d] == pytest.approx(r["mean"][0], rel=1e-6, abs=1e-7), d
         assert sigma[d] == pytest.approx(r["sd"][0], rel=1e-6), d

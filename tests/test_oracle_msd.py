@@ -24,6 +24,12 @@ def test_rejection_hand_worked():
     # masking: with few inliers a far point can survive (|100 - 22| < 2 * 43.6)
     m2, sd2, kept2 = msd.robust_mean_sd([1, 2, 3, 4, 100], 2.0, 10)
     assert kept2 == 5 and m2 == 22.0
+    # passes over the values: the estimate, the pass that drops 1000, the pass that changes
+    # nothing; with nothing to drop, the estimate and one pass; with no rejection, the estimate
+    assert msd.robust_mean_sd(v, 2.0, 10, with_passes=True)[3] == 3
+    assert msd.robust_mean_sd([1, 2, 3, 4, 100], 2.0, 10, with_passes=True)[3] == 2
+    assert msd.robust_mean_sd(v, 2.0, 0, with_passes=True)[3] == 1
+    assert msd.robust_mean_sd(v, 2.0, 1, with_passes=True)[3] == 2
 
 
 def test_decimate_sums():
