@@ -187,6 +187,9 @@ def main():
                     help="tiles of 64 x 4096 to train the learned proposal on (0: skip)")
     ap.add_argument("--proposal-eval", type=int, default=8192, help="held-out evaluation tiles")
     ap.add_argument("--proposal-batch", type=int, default=256)
+    ap.add_argument("--no-msd", action="store_true", help="skip the noise-statistics section")
+    ap.add_argument("--msd-tau", type=float, default=3.0)
+    ap.add_argument("--msd-iter", type=int, default=10)
     ap.add_argument("--batch-beams", type=int, default=32,
                     help="beams of the batched multi-beam run (0: skip)")
     ap.add_argument("--batch-dm-scale", type=int, default=8,
@@ -427,6 +430,10 @@ def main():
                          f"(FP64 oracle, {spent:.1f} s)"}
         log(f"[bench] cpu oracle: {cpu['value']:.3e} DM*samples/s on {cpu['cores']} threads")
 
+    msd_res = None
+    if not args.no_msd:
+        msd_res = msd_section(args, dev, x, w)
+
     batch = None
     if args.batch_beams > 0:
         torch.cuda.empty_cache()
@@ -476,6 +483,8 @@ def main():
         out["mean_loss_vs_exhaustive"] = methods[args.method]["mean_loss"]
     if batch is not None:
         out["batch"] = batch
+    if msd_res is not None:
+        out["msd"] = msd_res
     if served is not None:
         out["serving"] = served
     if prop is not None:
@@ -528,6 +537,41 @@ def sweep(dev) -> dict:
             res["l_end"].append(point(m, 1024, 131072, L))
     res["small_exhaustive"] = point("exh", 64, 65536, 256)
     return {"sweep": res, "unit_note": "ms per search (planes + candidates), one MI355X"}
+
+
+def msd_section(args, dev, x, w) -> dict:
+    """Noise statistics of the beam (spd_msd): mean and sigma per DM row with iterative
+    rejection, and sigma of every power-of-two decimation up to L_end.  Each pass reads the
+    row's samples once; the kernel reports how many passes each row took, so the algorithmic
+    bytes are 4 B x samples x passes."""
+    import torch
+    from paper_1910_08324_amd import msd as M
+
+    levels = int(w.l_end).bit_length()                  # widths 1, 2, .., 2^(levels-1) = L_end
+    for _ in range(2):
+        out = M.msd(x, levels, tau=args.msd_tau, max_iter=args.msd_iter, with_passes=True)
+    torch.cuda.synchronize()
+    passes = out[4].to(torch.float64)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        M.msd(x, levels, tau=args.msd_tau, max_iter=args.msd_iter)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = float(passes.sum().item()) * w.n * 4
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    res = {"levels": levels, "tau": args.msd_tau, "max_iter": args.msd_iter, "ms": round(ms, 4),
+           "dm_samples_per_s": w.n_dm * w.n / (ms * 1e-3),
+           "passes_mean": round(float(passes.mean().item()), 3),
+           "passes_max": int(passes.max().item()),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "algorithmic_bytes": nbytes, "kernel": "spdm::msd_kernel"}}
+    log(f"[bench] msd: {ms:.3f} ms for {w.n_dm} x {w.n}, {levels} levels, {res['passes_mean']} "
+        f"passes per row on average: {gbs:.0f} GB/s of sample reads ({gbs / HBM_PEAK_GBS:.3f} of HBM)")
+    return res
 
 
 def batch_section(args, dev) -> dict:
