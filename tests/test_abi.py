@@ -288,3 +288,27 @@ def test_copy_rows_argument_checks(lib):
     assert lib.spd_copy_rows(P(256), 10, P(512), 10, 70000, 4, None) == spd.SPD_EINVAL
     assert lib.spd_copy_rows(None, 0, None, 0, 0, 0, None) == spd.SPD_OK
     assert lib.spd_copy_rows(None, 0, None, 0, 3, 0, None) == spd.SPD_OK
+
+
+def test_msd_argument_checks(lib):
+    """spd_msd_workspace / spd_msd reject bad sizes, a short or unaligned workspace and NULL
+    outputs before any launch."""
+    from paper_1910_08324_amd import msd as M
+    L = M.lib()
+    P, i64 = ctypes.c_void_p, ctypes.c_int64
+    b = i64()
+    assert L.spd_msd_workspace(4, 1, 1, ctypes.byref(b)) == spd.SPD_EINVAL        # n_in < 2
+    assert L.spd_msd_workspace(4, 100, 8, ctypes.byref(b)) == spd.SPD_EINVAL      # 100 >> 7 < 2
+    assert L.spd_msd_workspace(4, 100, 25, ctypes.byref(b)) == spd.SPD_EINVAL     # > 24 levels
+    assert L.spd_msd_workspace(0, 100, 2, ctypes.byref(b)) == spd.SPD_EINVAL
+    assert L.spd_msd_workspace(4, 1 << 20, 14, ctypes.byref(b)) == spd.SPD_OK
+    need = b.value
+    # levels 9.. of every row fit: fewer than n / 256 values per row
+    assert need >= 4 * sum((1 << 20) >> k for k in range(9, 14)) * 8
+    args = lambda ws, wsb, mean=P(256), tau=3.0: L.spd_msd(P(4096), 1 << 20, 4, 1 << 20, 14, tau, 5,
+                                                           mean, P(512), None, None, None, ws,
+                                                           wsb, None)
+    assert args(P(1 << 20), need - 1) == spd.SPD_EWORKSPACE
+    assert args(P((1 << 20) + 8), need) == spd.SPD_EALIGN
+    assert args(P(1 << 20), need, mean=None) == spd.SPD_EINVAL
+    assert args(P(1 << 20), need, tau=0.0) == spd.SPD_EINVAL
