@@ -84,7 +84,8 @@ def launch_kernel_name(method: str, info, i: int) -> str:
         if info.launch_first_level[i] < 0:
             return "spd::scales_kernel"
         multi = "true" if int(info.segment) > 256 else "false"      # items per wave > 1
-        return f"spd::exh_kernel<true, {multi}>"
+        group = 16 if int(info.max_width) <= 4096 else 64          # widths per max-only group
+        return f"spd::exh_kernel<true, {multi}, {group}>"
     first = "true" if info.launch_first_level[i] == 0 else "false"
     return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}, false>"
 

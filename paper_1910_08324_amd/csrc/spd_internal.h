@@ -15,7 +15,8 @@ constexpr int kStepThreads = 256;     // threads per tile work-group
 constexpr int kGroup = 4;             // consecutive slots evaluated together by one thread
 constexpr int kExhSlots = 256;        // output slots per exhaustive work item (64 lanes x 4)
 constexpr int kExhBlock = 512;        // widths per LDS window refill in the exhaustive kernel
-constexpr int kExhGroup = 64;         // widths per max-only group (argmax recovered afterwards)
+constexpr int kExhGroup = 64;         // most widths per max-only group (argmax recovered afterwards)
+constexpr int kExhSmallGroupMax = 4096;  // largest L_end searched in groups of 16 widths
 constexpr int kSlabCap = 64;          // pre-candidates kept per (level, row, tile): one per lane
 constexpr int kExhSlabCap = 16;       // pre-candidates kept per exhaustive work item
 constexpr int kExhItemsPerWave = 4;   // work items per wave when every width fits one block

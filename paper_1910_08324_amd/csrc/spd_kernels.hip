@@ -520,10 +520,10 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel_bat
 //
 // Work item = (row d, 256 output slots starting at s0).  Lane l owns the 4 consecutive starts
 // s0 + 4l + v.  Widths are visited in increasing order with one running sum per start, in
-// groups of 64 widths: inside a group only the maximum is tracked (add, multiply, max per
+// groups of 16 or 64 widths: inside a group only the maximum is tracked (add, multiply, max per
 // start and width); after the group the best group, and the running sum entering it, are
 // kept.  The winning width inside the winning group is recovered at the end by replaying that
-// group's 64 steps with the same FP32 operations, so it is the smallest width attaining the
+// group's steps with the same FP32 operations, so it is the smallest width attaining the
 // maximum, exactly as a per-width argmax would give.
 // The input window z[s0 .. s0 + 256 + L_end) streams through a 1024-float LDS ring, 512 new
 // samples per block of 512 widths.  The ring's first 16 float4 are mirrored after its end, so a
@@ -545,9 +545,9 @@ __device__ __forceinline__ void ring_put(float4 *ring4, int i, float4 v) {   // 
     if (i < kGuard4) ring4[kRing4 + i] = v;
 }
 
-// 64 widths L0 .. L0+63 at the lane's 4 starts: running sums X, group maxima gm.  The window
+// G widths L0 .. L0+G-1 at the lane's 4 starts: running sums X, group maxima gm.  The window
 // z[s0 + 4 lane + L0 - 1 ..] is read from the LDS ring one float4 per 4 widths.
-template <bool CHECK, bool DENSE>
+template <bool CHECK, bool DENSE, int G>
 __device__ __forceinline__ void exh_group(const float4 *ring4, int jb4, int L0, ConstFloatPtr scale,
                                           const uint32_t *evalmask, int Lw, const int room[4],
                                           float X[4], float gm[4]) {
@@ -555,7 +555,7 @@ __device__ __forceinline__ void exh_group(const float4 *ring4, int jb4, int L0, 
     const v4f *win = reinterpret_cast<const v4f *>(ring4 + (jb4 & (kRing4 - 1)));
     v4f wa = win[0];
 #pragma unroll 4
-    for (int t = 0; t < kExhGroup / 4; ++t) {
+    for (int t = 0; t < G / 4; ++t) {
         const v4f wb = win[t + 1];
         const float w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
         const int L = L0 + 4 * t;
@@ -580,7 +580,10 @@ __device__ __forceinline__ void exh_group(const float4 *ring4, int jb4, int L0, 
     }
 }
 
-template <bool DENSE, bool MULTI>
+// G: widths per max-only group.  L_end up to 4096 takes groups of 16 (a shorter argmax replay
+// per start, which there costs as much as the width loop: 2x faster at L_end 256, 1.8x at 1024);
+// larger L_end groups of 64 (less bookkeeping per width).
+template <bool DENSE, bool MULTI, int G>
 __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
     __shared__ float4 ring4[kRing4 + kGuard4];
 
@@ -652,12 +655,12 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
             pf0 = load4(s0 + jn + lane * 4);
             pf1 = load4(s0 + jn + 256 + lane * 4);
         }
-        for (int gi = 0; gi < kExhBlock / kExhGroup; ++gi) {
-            const int L0 = b * kExhBlock + gi * kExhGroup + 1;
+        for (int gi = 0; gi < kExhBlock / G; ++gi) {
+            const int L0 = b * kExhBlock + gi * G + 1;
             if (L0 > Lw) break;
             // wave-uniform: every width of the group fits at every start of the work item
-            const bool fast = (L0 + kExhGroup - 1 <= Lw) &&
-                              ((int64_t)s0 + kExhSlots - 1 + L0 + kExhGroup - 1 <= n_in);
+            const bool fast = (L0 + G - 1 <= Lw) &&
+                              ((int64_t)s0 + kExhSlots - 1 + L0 + G - 1 <= n_in);
             float Xs[4], gm[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -666,14 +669,14 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
             }
             const int jb4 = ro4 + lane + ((L0 - 1) >> 2);
             if (fast)
-                exh_group<false, DENSE>(ring4, jb4, L0, (ConstFloatPtr)srow, A.evalmask, Lw, room, X, gm);
+                exh_group<false, DENSE, G>(ring4, jb4, L0, (ConstFloatPtr)srow, A.evalmask, Lw, room, X, gm);
             else
-                exh_group<true, DENSE>(ring4, jb4, L0, (ConstFloatPtr)srow, A.evalmask, Lw, room, X, gm);
+                exh_group<true, DENSE, G>(ring4, jb4, L0, (ConstFloatPtr)srow, A.evalmask, Lw, room, X, gm);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 if (gm[v] > best[v]) {
                     best[v] = gm[v];
-                    bg[v] = (L0 - 1) / kExhGroup;
+                    bg[v] = (L0 - 1) / G;
                     bx[v] = Xs[v];
                 }
             }
@@ -695,9 +698,9 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
     for (int v = 0; v < 4; ++v) {
         if (best[v] == SPD_NEG_INF) continue;
         const int sv = s0 + 4 * lane + v;
-        const int Lb = bg[v] * kExhGroup + 1;
+        const int Lb = bg[v] * G + 1;
         float Xr = bx[v], bm = SPD_NEG_INF;
-        for (int t = 0; t < kExhGroup; ++t) {
+        for (int t = 0; t < G; ++t) {
             const int L = Lb + t;
             if (L > Lw) break;
             Xr += (nblk == 1) ? ring[(4 * ro4 + 4 * lane + v + L - 1) & (4 * kRing4 - 1)]
@@ -1069,15 +1072,25 @@ int launch_exhaustive(const ExhArgs &a, bool dense, void *stream) {
     const int64_t per_row = (a.n_seg + a.segs_per_wave - 1) / a.segs_per_wave;
     const dim3 grid((unsigned)((int64_t)a.n_dm * per_row));
     const bool multi = a.segs_per_wave > 1;
+    // groups of 16 widths up to L_end 4096, of 64 above (measured crossover on gfx950)
+    const bool small = a.l_end <= kExhSmallGroupMax;
     hipStream_t st = (hipStream_t)stream;
-    if (dense && multi)
-        hipLaunchKernelGGL((exh_kernel<true, true>), grid, dim3(64), 0, st, a);
-    else if (dense)
-        hipLaunchKernelGGL((exh_kernel<true, false>), grid, dim3(64), 0, st, a);
-    else if (multi)
-        hipLaunchKernelGGL((exh_kernel<false, true>), grid, dim3(64), 0, st, a);
-    else
-        hipLaunchKernelGGL((exh_kernel<false, false>), grid, dim3(64), 0, st, a);
+    if (multi) {
+        if (dense)
+            hipLaunchKernelGGL((exh_kernel<true, true, 16>), grid, dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL((exh_kernel<false, true, 16>), grid, dim3(64), 0, st, a);
+    } else if (small) {
+        if (dense)
+            hipLaunchKernelGGL((exh_kernel<true, false, 16>), grid, dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL((exh_kernel<false, false, 16>), grid, dim3(64), 0, st, a);
+    } else {
+        if (dense)
+            hipLaunchKernelGGL((exh_kernel<true, false, 64>), grid, dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL((exh_kernel<false, false, 64>), grid, dim3(64), 0, st, a);
+    }
     return (int)hipGetLastError();
 }
 
