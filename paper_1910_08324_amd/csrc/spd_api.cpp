@@ -44,14 +44,14 @@ bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 // times; its widths are off_k + m 2^k, m = 1..L^k_max, with off_k = sum_{j<k} 2^j L^j_max.  The
 // shifted decimation x^{k+1}[n] = x^k[2n + L^k_max] + x^k[2n + L^k_max + 1] needs L^k_max even.
 // Exhaustive search: 256-slot items per wave when the caller leaves it to the library.  Four
-// items amortise the window fill and keep the next item's samples in flight; measured on gfx950
-// they gain 5-20% up to L_end 256, and at L_end 512 on short rows, as long as the launch still
-// has some 32 waves per compute unit (with fewer, one item per wave keeps more of them busy).
+// items amortise the window fill over a short row's few items and keep the next item's samples
+// in flight; measured on gfx950 they gain 25-40% on rows of at most 16384 slots from L_end 128
+// to 512, as long as the launch keeps some 32 waves per compute unit.  Elsewhere one item per
+// wave is as fast or faster.
 int exh_default_items(int32_t l_end, int32_t n_dm, int32_t n_out) {
     const int64_t waves4 = (int64_t)n_dm * ceil_div(ceil_div(n_out, spd::kExhSlots), 4);
     if (waves4 < 8192) return 1;
-    if (l_end <= 256) return 4;
-    if (l_end <= 512 && n_out <= 16384) return 4;
+    if (l_end >= 128 && l_end <= spd::kExhBlock && n_out <= 16384) return 4;
     return 1;
 }
 
