@@ -269,3 +269,32 @@ def test_generic_width_sets(dev, cfgkw, levels):
     R = oplanes.planes(x, mu, sg, levels(l_end))
     parity.check_planes(P, R, x, mu, sg, 30011, what=str(cfgkw))
     parity.check_candidates(C, R, 4.0, what=str(cfgkw))
+
+
+@pytest.mark.parametrize("method", ["ig1", "bd16", "exh"])
+def test_concurrent_streams_match_sequential(dev, method):
+    """Searches on separate streams (default priority), each with its own buffers, run
+    concurrently and give bitwise the results of running them one after the other."""
+    from paper_1910_08324_amd import spd
+    cfg = spd.Config(method, 400, threshold=4.0)
+    inputs = []
+    for i in range(3):
+        x, mu, sg = make_input(6, 30011 + 1000 * i, 60 + i, pulses=[synth.Pulse(2, 9000, 80, 14.0)])
+        inputs.append(tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (x, mu, sg)))
+    seq = []
+    for xd, mu_d, sg_d in inputs:
+        r = spd.search(xd, mu_d, sg_d, cfg, cand_cap=1 << 16)
+        torch.cuda.synchronize()
+        seq.append((r.planes_host(), r.candidates_host()))
+    streams = [torch.cuda.Stream(device=dev) for _ in inputs]
+    main = torch.cuda.current_stream(dev)
+    res = []
+    for s, (xd, mu_d, sg_d) in zip(streams, inputs):
+        s.wait_stream(main)
+        with torch.cuda.stream(s):
+            res.append(spd.search(xd, mu_d, sg_d, cfg, cand_cap=1 << 16, stream=s.cuda_stream))
+    torch.cuda.synchronize()
+    for (P0, C0), r in zip(seq, res):
+        for a, b in zip(P0, r.planes_host()):
+            assert np.array_equal(a["Y"], b["Y"]) and np.array_equal(a["W"], b["W"])
+        assert np.array_equal(C0, r.candidates_host())
