@@ -4,16 +4,17 @@
  * A batch is a set of beams (blocks of dedispersed DM rows, each with its own number of rows and
  * samples) searched with the same BoxDIT or IGRID parameters (Sections 3.1, 3.2 of Adamek &
  * Armour, arXiv:1910.08324).  Every cascade step of the search runs as ONE kernel launch over all
- * beams: a persistent grid walks the (beam, DM row, tile) work items of the whole batch.  The
- * peak finder then runs per beam.  Every beam's planes and candidates are bitwise identical to
- * those of spd_search on that beam alone with the same parameters.
+ * beams: a persistent grid walks the (beam, DM row, tile) work items of the whole batch; each
+ * pass of the peak finder is likewise one launch over the waves of every beam.  Every beam's
+ * planes and candidates are bitwise identical to those of spd_search on that beam alone with the
+ * same parameters.
  *
  * Use:
  *   1. spd_batch_plan: workspace and descriptor-table sizes.
  *   2. spd_batch_table: the library writes the batch's descriptor table into a HOST buffer;
  *      the caller copies those bytes to device memory (the library never copies or allocates).
- *      The table depends on the beams' pointers and on the workspace address, so it is made again
- *      when either changes.
+ *      The table depends on the beams' pointers (inputs, planes, candidate buffers) and on the
+ *      workspace address, so it is made again when any of them changes.
  *   3. spd_batch_search (asynchronous on the stream), as often as wanted.
  * The exhaustive method is not batched (SPD_EINVAL): it is bound by arithmetic, not by launches.
  */

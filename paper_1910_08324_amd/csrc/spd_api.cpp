@@ -693,8 +693,8 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
     return SPD_OK;
 }
 
-int run_peaks(const spd_params *params, const Prepared &P, int32_t n_dm, int64_t t0,
-              spd_candidate *cand, int64_t cand_cap, int64_t *cand_count, void *hip_stream) {
+spd::PeakArgs peak_args(const spd_params *params, const Prepared &P, int32_t n_dm, int64_t t0,
+                        spd_candidate *cand, int64_t cand_cap, int64_t *cand_count) {
     const Layout &L = P.L;
     const spd_plan_info &I = L.info;
     spd::PeakArgs a;
@@ -727,6 +727,12 @@ int run_peaks(const spd_params *params, const Prepared &P, int32_t n_dm, int64_t
         a.tile_slots[i] = L.tile_slots[i];
     }
     for (int i = 0; i <= I.n_levels; ++i) a.slab_base[i] = L.slab_base[i];
+    return a;
+}
+
+int run_peaks(const spd_params *params, const Prepared &P, int32_t n_dm, int64_t t0,
+              spd_candidate *cand, int64_t cand_cap, int64_t *cand_count, void *hip_stream) {
+    const spd::PeakArgs a = peak_args(params, P, n_dm, t0, cand, cand_cap, cand_count);
     const int err = spd::launch_peaks(a, hip_stream);
     if (err) return hip_fail(err);
     return SPD_OK;
@@ -743,6 +749,9 @@ struct BatchPlan {
     int64_t ws_total = 0;
     int64_t table_bytes = 0;
     int64_t base_off = 0;       // offset of the item_base arrays in the table
+    int64_t peak_off = 0;       // offset of the per-beam peak-finder arguments
+    int64_t wbase_off = 0;      // offset of the peak finder's wave_base array
+    int64_t n_waves = 0;        // peak-finder waves of all beams
     int n_steps = 0;
 };
 
@@ -772,7 +781,11 @@ int batch_plan(const spd_params *params, int32_t n_beams, const spd_beam *beams,
     B->n_steps = (int)B->L[0].steps.size();
     B->ws_total = off;
     B->base_off = round_up((int64_t)B->n_steps * n_beams * (int64_t)sizeof(spd::BeamView), 256);
-    B->table_bytes = B->base_off + (int64_t)B->n_steps * (n_beams + 1) * 8;
+    B->peak_off = round_up(B->base_off + (int64_t)B->n_steps * (n_beams + 1) * 8, 256);
+    B->wbase_off = round_up(B->peak_off + (int64_t)n_beams * (int64_t)sizeof(spd::PeakArgs), 256);
+    B->table_bytes = B->wbase_off + (int64_t)(n_beams + 1) * 8;
+    B->n_waves = 0;
+    for (int b = 0; b < n_beams; ++b) B->n_waves += B->L[b].n_waves;
     return SPD_OK;
 }
 
@@ -817,6 +830,19 @@ spd::BeamView beam_view(const spd_params *params, const BatchPlan &B, const spd_
         v.slots[j] = st.lv[j].slots;
     }
     return v;
+}
+
+// the single-beam view of beam b of a batch (its layout, workspace and planes)
+Prepared beam_prepared(const spd_params *params, const BatchPlan &B, const spd_beam &bm, int b,
+                       char *ws_base) {
+    Prepared P;
+    P.s = B.s;
+    P.L = B.L[b];
+    P.ws = ws_base + B.ws_off[b];
+    const bool planes = params->flags & SPD_WRITE_PLANES;
+    P.Y = planes ? bm.snr : reinterpret_cast<float *>(P.ws + P.L.off_Y);
+    P.W = planes ? bm.width : reinterpret_cast<uint16_t *>(P.ws + P.L.off_W);
+    return P;
 }
 
 int check_beam(const spd_params *params, const BatchPlan &B, const spd_beam &bm, int b) {
@@ -929,6 +955,19 @@ int spd_batch_table(const spd_params *params, int32_t n_beams, const spd_beam *b
         }
         base[(int64_t)si * (n_beams + 1) + n_beams] = items;
     }
+    if (params->flags & SPD_WRITE_CANDIDATES) {
+        spd::PeakArgs *pk = reinterpret_cast<spd::PeakArgs *>(t + B.peak_off);
+        int64_t *wb = reinterpret_cast<int64_t *>(t + B.wbase_off);
+        int64_t waves = 0;
+        for (int b = 0; b < n_beams; ++b) {
+            const Prepared P = beam_prepared(params, B, beams[b], b, static_cast<char *>(workspace));
+            pk[b] = peak_args(params, P, beams[b].n_dm, beams[b].t0, beams[b].cand,
+                              beams[b].cand_cap, beams[b].cand_count);
+            wb[b] = waves;
+            waves += B.L[b].n_waves;
+        }
+        wb[n_beams] = waves;
+    }
     return SPD_OK;
 }
 
@@ -962,18 +1001,14 @@ int spd_batch_search(const spd_params *params, int32_t n_beams, const spd_beam *
         if (err) return hip_fail(err);
     }
     if (!(params->flags & SPD_WRITE_CANDIDATES)) return SPD_OK;
-    for (int b = 0; b < n_beams; ++b) {
-        Prepared P;
-        P.s = B.s;
-        P.L = B.L[b];
-        P.ws = static_cast<char *>(workspace) + B.ws_off[b];
-        const bool planes = params->flags & SPD_WRITE_PLANES;
-        P.Y = planes ? beams[b].snr : reinterpret_cast<float *>(P.ws + P.L.off_Y);
-        P.W = planes ? beams[b].width : reinterpret_cast<uint16_t *>(P.ws + P.L.off_W);
-        st = run_peaks(params, P, beams[b].n_dm, beams[b].t0, beams[b].cand, beams[b].cand_cap,
-                       beams[b].cand_count, hip_stream);
-        if (st != SPD_OK) return st;
-    }
+    // the peak finder of every beam: one launch per pass, arguments from the table
+    spd::PeakBatchArgs pb;
+    pb.tab = reinterpret_cast<const spd::PeakArgs *>(t + B.peak_off);
+    pb.wave_base = reinterpret_cast<const int64_t *>(t + B.wbase_off);
+    pb.n_waves = B.n_waves;
+    pb.n_beams = n_beams;
+    const int err = spd::launch_peaks_batch(pb, hip_stream);
+    if (err) return hip_fail(err);
     return SPD_OK;
 }
 

@@ -185,6 +185,16 @@ int launch_step_batch(const StepBatchArgs &a, int fam, int lds_bytes, int grid, 
 uint64_t family_mask(int fam, int pattern);
 int launch_exhaustive(const ExhArgs &a, bool dense, void *stream);
 int launch_peaks(const PeakArgs &a, void *stream);
+
+// the peak finder over every beam of a batch: a device table of PeakArgs (16-byte aligned) and
+// the first global wave index of each beam (n_beams + 1 entries)
+struct PeakBatchArgs {
+    const PeakArgs *tab;
+    const int64_t *wave_base;
+    int64_t n_waves;
+    int32_t n_beams;
+};
+int launch_peaks_batch(const PeakBatchArgs &a, void *stream);
 const char *hip_error_text(int err);
 
 }  // namespace spd

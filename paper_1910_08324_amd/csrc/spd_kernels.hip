@@ -788,7 +788,10 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
 // output in (level, dm, start) order without a global sort: per-wave survivor counts (each
 // slab's entries sorted in the wave), one scan, scatter.
 // ----------------------------------------------------------------------------------------
-__device__ __forceinline__ bool peak_test(const PeakArgs &A, int k, int d, int m, float y) {
+// The helpers take the arguments either from the launch (one beam) or from a per-beam table in
+// the constant address space (a batch); PA is the (qualified) PeakArgs type.
+template <class PA>
+__device__ __forceinline__ bool peak_test(PA &A, int k, int d, int m, float y) {
     const float *P = A.Y + A.level_off[k];
     const int64_t pitch = A.level_pitch[k];
     const int slots = A.level_slots[k];
@@ -813,7 +816,8 @@ struct SlabPos {
     int k, d, t, mlo, mhi;
 };
 
-__device__ __forceinline__ SlabPos slab_decode(const PeakArgs &A, int64_t s) {
+template <class PA>
+__device__ __forceinline__ SlabPos slab_decode(PA &A, int64_t s) {
     SlabPos p;
     int k = 0;
     while (k + 1 < A.n_levels && s >= A.slab_base[k + 1]) ++k;
@@ -826,7 +830,8 @@ __device__ __forceinline__ SlabPos slab_decode(const PeakArgs &A, int64_t s) {
     return p;
 }
 
-__device__ __forceinline__ float plane_at(const PeakArgs &A, int k, int d, int m) {
+template <class PA>
+__device__ __forceinline__ float plane_at(PA &A, int k, int d, int m) {
     return A.Y[A.level_off[k] + (int64_t)d * A.level_pitch[k] + m];
 }
 
@@ -845,10 +850,9 @@ __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key, int lane) {
     return key;
 }
 
-__global__ __launch_bounds__(256) void peak_count_kernel(const PeakArgs A) {
-    const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= A.n_waves) return;
+// count pass of wave w of a beam
+template <class PA>
+__device__ __forceinline__ void peak_count_wave(PA &A, int w, int lane) {
     const int64_t sbeg = (int64_t)w * A.slabs_per_wave;
     const int64_t send = min(sbeg + A.slabs_per_wave, A.n_slabs);
     int64_t total = 0;
@@ -897,8 +901,15 @@ __global__ __launch_bounds__(256) void peak_count_kernel(const PeakArgs A) {
     if (lane == 0) A.wave_tot[w] = total;
 }
 
-__global__ __launch_bounds__(1024) void peak_scan_kernel(const PeakArgs A) {
-    __shared__ int64_t part[1024];
+__global__ __launch_bounds__(256) void peak_count_kernel(const PeakArgs A) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= A.n_waves) return;
+    peak_count_wave(A, w, threadIdx.x & 63);
+}
+
+// exclusive scan of a beam's per-wave totals by one 1024-thread work-group
+template <class PA>
+__device__ __forceinline__ void peak_scan_block(PA &A, int64_t *part) {
     const int t = threadIdx.x;
     const int per = (A.n_waves + 1023) / 1024;
     int64_t loc = 0;
@@ -925,8 +936,13 @@ __global__ __launch_bounds__(1024) void peak_scan_kernel(const PeakArgs A) {
     if (t == 1023) *A.cand_count = part[1023];
 }
 
-__device__ __forceinline__ void put_cand(const PeakArgs &A, int64_t idx, int k, int d, int m,
-                                         float y) {
+__global__ __launch_bounds__(1024) void peak_scan_kernel(const PeakArgs A) {
+    __shared__ int64_t part[1024];
+    peak_scan_block(A, part);
+}
+
+template <class PA>
+__device__ __forceinline__ void put_cand(PA &A, int64_t idx, int k, int d, int m, float y) {
     if (idx >= A.cand_cap) return;
     spd_candidate c;
     c.start = A.t0 + ((int64_t)m << A.level_shift[k]);
@@ -937,10 +953,9 @@ __device__ __forceinline__ void put_cand(const PeakArgs &A, int64_t idx, int k, 
     A.cand[idx] = c;
 }
 
-__global__ __launch_bounds__(256) void peak_scatter_kernel(const PeakArgs A) {
-    const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (w >= A.n_waves) return;
+// scatter pass of wave w of a beam
+template <class PA>
+__device__ __forceinline__ void peak_scatter_wave(PA &A, int w, int lane) {
     const int64_t sbeg = (int64_t)w * A.slabs_per_wave;
     const int64_t send = min(sbeg + A.slabs_per_wave, A.n_slabs);
     int64_t off = A.wave_off[w];
@@ -980,6 +995,50 @@ __global__ __launch_bounds__(256) void peak_scatter_kernel(const PeakArgs A) {
             off += nsurv;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void peak_scatter_kernel(const PeakArgs A) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= A.n_waves) return;
+    peak_scatter_wave(A, w, threadIdx.x & 63);
+}
+
+// Batched: the peak-finder arguments of every beam in a table in the constant address space
+// (read with scalar loads), the waves of all beams in one index space: wave i belongs to beam b
+// with wave_base[b] <= i < wave_base[b + 1].  One launch per pass for the whole batch; the scan
+// takes one work-group per beam.
+typedef __attribute__((address_space(4))) const PeakArgs CPeakArgs;
+
+__device__ __forceinline__ int peak_beam_of(const PeakBatchArgs &B, int64_t wg) {
+    const ConstI64Ptr base = (ConstI64Ptr)B.wave_base;
+    int lo = 0, hi = B.n_beams - 1;                     // last b with base[b] <= wg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= wg) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void peak_count_batch_kernel(const PeakBatchArgs B) {
+    const int64_t wg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wg >= B.n_waves) return;
+    const int b = peak_beam_of(B, wg);
+    CPeakArgs &A = ((CPeakArgs *)B.tab)[b];
+    peak_count_wave(A, (int)(wg - ((ConstI64Ptr)B.wave_base)[b]), threadIdx.x & 63);
+}
+
+__global__ __launch_bounds__(1024) void peak_scan_batch_kernel(const PeakBatchArgs B) {
+    __shared__ int64_t part[1024];
+    CPeakArgs &A = ((CPeakArgs *)B.tab)[blockIdx.x];
+    peak_scan_block(A, part);
+}
+
+__global__ __launch_bounds__(256) void peak_scatter_batch_kernel(const PeakBatchArgs B) {
+    const int64_t wg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wg >= B.n_waves) return;
+    const int b = peak_beam_of(B, wg);
+    CPeakArgs &A = ((CPeakArgs *)B.tab)[b];
+    peak_scatter_wave(A, (int)(wg - ((ConstI64Ptr)B.wave_base)[b]), threadIdx.x & 63);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -1103,6 +1162,20 @@ int launch_peaks(const PeakArgs &a, void *stream) {
     err = (int)hipGetLastError();
     if (err) return err;
     hipLaunchKernelGGL(peak_scatter_kernel, grid, dim3(256), 0, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+int launch_peaks_batch(const PeakBatchArgs &a, void *stream) {
+    if (a.n_waves <= 0) return 0;
+    const dim3 grid((unsigned)((a.n_waves + 3) / 4));
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(peak_count_batch_kernel, grid, dim3(256), 0, st, a);
+    int err = (int)hipGetLastError();
+    if (err) return err;
+    hipLaunchKernelGGL(peak_scan_batch_kernel, dim3((unsigned)a.n_beams), dim3(1024), 0, st, a);
+    err = (int)hipGetLastError();
+    if (err) return err;
+    hipLaunchKernelGGL(peak_scatter_batch_kernel, grid, dim3(256), 0, st, a);
     return (int)hipGetLastError();
 }
 

@@ -259,16 +259,20 @@ def test_batch_plan_and_table_host(lib):
                              host.ctypes.data_as(ctypes.c_void_p), tb.value) == 0
     info = spd.plan(spd.Config("ig1", 700), 3, 20011)
     steps = info.n_launches
-    base = host[-steps * (len(shapes) + 1) * 8:].view(np.int64).reshape(steps, len(shapes) + 1)
+    nb = len(shapes)
+    # the first step's item bases (work items of the beams before each), then one array per step
+    items = [0]
+    for n_dm, n in shapes:
+        items.append(items[-1] + n_dm * spd.plan(spd.Config("ig1", 700), n_dm, n).n_segments)
+    words = host[: len(host) // 8 * 8].view(np.int64)
+    at = [i for i in range(0, len(words) - nb) if list(words[i: i + nb + 1]) == items]
+    assert len(at) == 1
+    base = words[at[0]: at[0] + steps * (nb + 1)].reshape(steps, nb + 1)
     for si in range(steps):
-        items = [0]
-        for n_dm, n in shapes:
-            inf = spd.plan(spd.Config("ig1", 700), n_dm, n)
-            tiles = inf.n_segments if si == 0 else None
-            items.append(items[-1] + (n_dm * tiles if tiles is not None else 0))
         assert base[si, 0] == 0 and np.all(np.diff(base[si]) > 0)
-        if si == 0:
-            assert list(base[0]) == items
+    # candidates requested: the table ends with the peak finder's first wave of every beam
+    wave_base = words[-(nb + 1):]
+    assert wave_base[0] == 0 and np.all(np.diff(wave_base) > 0)
     pe, keep2 = spd.Config("exh", 100).params()
     assert L.spd_batch_plan(ctypes.byref(pe), 1, arr, ctypes.byref(wsb), ctypes.byref(tb)) == spd.SPD_EINVAL
     assert L.spd_batch_plan(ctypes.byref(p), 0, arr, ctypes.byref(wsb), ctypes.byref(tb)) == spd.SPD_EINVAL
