@@ -431,6 +431,9 @@ def main():
                          f"(FP64 oracle, {spent:.1f} s)"}
         log(f"[bench] cpu oracle: {cpu['value']:.3e} DM*samples/s on {cpu['cores']} threads")
 
+    hbm = hbm_section(dev, x)
+    torch.cuda.empty_cache()
+
     msd_res = None
     if not args.no_msd:
         msd_res = msd_section(args, dev, x, w)
@@ -484,6 +487,7 @@ def main():
         out["mean_loss_vs_exhaustive"] = methods[args.method]["mean_loss"]
     if batch is not None:
         out["batch"] = batch
+    out["hbm_reference"] = hbm
     if msd_res is not None:
         out["msd"] = msd_res
     if served is not None:
@@ -538,6 +542,36 @@ def sweep(dev) -> dict:
             res["l_end"].append(point(m, 1024, 131072, L))
     res["small_exhaustive"] = point("exh", 64, 65536, 256)
     return {"sweep": res, "unit_note": "ms per search (planes + candidates), one MI355X"}
+
+
+def hbm_section(dev, x) -> dict:
+    """Plain streaming rates of this GPU with torch's own kernels on the beam's 4 GiB: write-only
+    (fill), read-only (sum) and copy, for comparison with the search's dominant launch, whose
+    traffic is three quarters writes."""
+    import torch
+    y = torch.empty_like(x)
+    nbytes = x.numel() * 4
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def rate(fn, moved):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(moved / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9, 1)
+
+    res = {"bytes": nbytes,
+           "write_gbs": rate(lambda: y.fill_(1.0), nbytes),
+           "read_gbs": rate(lambda: x.sum(), nbytes),
+           "copy_gbs": rate(lambda: y.copy_(x), 2 * nbytes),
+           "peak_gbs": HBM_PEAK_GBS}
+    del y
+    log(f"[bench] hbm with torch kernels: write {res['write_gbs']} GB/s, read {res['read_gbs']} GB/s, "
+        f"copy {res['copy_gbs']} GB/s (read + write)")
+    return res
 
 
 def msd_section(args, dev, x, w) -> dict:
