@@ -267,15 +267,13 @@ class StreamServer:
                 taken.add(r.beam)
                 # this beam's queued blocks, in order, searched as one window
                 grp = [r] + [q for q in queued[qi + 1:] if q.beam == r.beam][: self.coalesce - 1]
-                t, r0 = b.t_end, b.r0
-                for q in grp:
-                    t += q.block.shape[1]
-                    q.region = (r0, max(r0, self._region_end(t)))
-                    r0 = q.region[1]
                 groups.append(grp)
-                windows.append(self._window(grp[0].region[0], r0, t))
+                windows.append(self._group_window(grp))
             # the batch's workspace must fit a free range of the arena (the budget): the latest
-            # groups wait until it does, first come first served
+            # groups wait until it does, first come first served.  With nothing in flight the
+            # whole arena is free, so the first group searches fewer of its blocks until its
+            # window fits; a single block whose window exceeds the budget is an error (waiting
+            # would never admit it).
             off, wsb = None, 0
             while groups:
                 dims = [(self.beams[g[0].beam].n_dm, w[1], w[2])
@@ -286,14 +284,34 @@ class StreamServer:
                 off = self.arena.alloc(wsb)
                 if off is not None:
                     break
-                groups.pop()
-                windows.pop()
+                if len(groups) > 1 or self.arena.in_use > 0:
+                    groups.pop()
+                    windows.pop()
+                elif len(groups[0]) > 1:
+                    groups[0].pop()
+                    windows[0] = self._group_window(groups[0])
+                else:
+                    q = groups[0][0]
+                    raise RuntimeError(f"beam {q.beam} block {q.index}: the search workspace of its "
+                                       f"window ({wsb} bytes) exceeds the HBM budget "
+                                       f"({self.arena.size} bytes)")
             if not groups:
                 return
             for grp in groups:
                 for q in grp:
                     self.queue.remove(q)
             self._launch(slot, groups, windows, off, wsb)
+
+    def _group_window(self, grp: List[Request]) -> Optional[Tuple[int, int, int]]:
+        """Assign the regions of a beam's queued blocks searched together and return the window
+        of the group (None if every region is empty)."""
+        b = self.beams[grp[0].beam]
+        t, r0 = b.t_end, b.r0
+        for q in grp:
+            t += q.block.shape[1]
+            q.region = (r0, max(r0, self._region_end(t)))
+            r0 = q.region[1]
+        return self._window(grp[0].region[0], r0, t)
 
     def _region_end(self, t_end: int) -> int:
         g = self.grain

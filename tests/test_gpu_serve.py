@@ -107,18 +107,60 @@ def test_alone_equals_mixed(S):
 
 
 def test_budget_limits_admission(S):
+    """A 1-byte budget admits only blocks whose regions are still empty (no workspace); the
+    first block whose own window needs memory is an error, not a wait that never ends."""
     n_dm = 16
-    beams = {b: stream(b, n_dm, [4096] * 4, seed=2) for b in range(3)}
+    beams = {b: stream(b, n_dm, [1024] * 4, seed=2) for b in range(3)}
     srv = S.StreamServer(l_end=2048, threshold=4.5, max_block=8192, slots=3, hbm_budget=1)
     for b in beams:
         srv.open_beam(b, n_dm)
     for i in range(4):
         for b in beams:
             srv.submit(b, beams[b][i])
-    srv.poll()
-    # nothing whose window needs memory fits a 1-byte budget; blocks with empty regions pass
-    assert all(r.region[0] == r.region[1] for r in srv.results)
+    srv.poll()                                    # the first blocks' regions are empty
     assert len(srv.queue) > 0
+    with pytest.raises(RuntimeError, match="exceeds the HBM budget"):
+        srv.drain()
+    assert len(srv.results) > 0
+    assert all(r.region[0] == r.region[1] for r in srv.results)
+
+
+def test_budget_shrinks_coalesced_windows(S):
+    """A budget that holds one block's window but not a window of several coalesced blocks:
+    the server searches fewer blocks per window instead of waiting for memory that never frees,
+    and every block's candidates equal those of an unconstrained server."""
+    n_dm = 16
+    beams = {b: stream(b, n_dm, sizes_for(b, 8, seed=9), seed=9) for b in range(3)}
+
+    def serve(budget):
+        srv = S.StreamServer(l_end=2048, threshold=4.5, max_block=8192, slots=2,
+                             hbm_budget=budget, coalesce=8)
+        for b in beams:
+            srv.open_beam(b, n_dm)
+        for i in range(8):                       # everything queued first: windows coalesce
+            for b in beams:
+                srv.submit(b, beams[b][i])
+        peak, windows = 0, []
+        while srv.queue or any(s.busy for s in srv.slots):
+            srv.poll()
+            peak = max(peak, srv.arena.in_use)
+            windows += [len(g) for s in srv.slots if s.busy for g in s.groups]
+        return srv, peak, windows
+
+    free, _, wfree = serve(64 << 30)
+    probe = S.StreamServer(l_end=2048, threshold=4.5, max_block=8192)
+    probe.open_beam(0, n_dm)
+    g = probe.grain
+    one, _ = probe._batch_plan([(n_dm, 8192 + 2048 + 4 * g, 8192 + 4 * g)])
+    tight, peak, wtight = serve(one + 512)
+    say(f"  blocks per window: free {max(wfree)}, tight {max(wtight)}; arena peak {peak}")
+    assert max(wfree) > 1                        # the unconstrained server coalesced
+    assert 0 < peak <= one + 512
+    key = lambda r: (r.beam, r.index)
+    A, B = sorted(free.results, key=key), sorted(tight.results, key=key)
+    assert [key(r) for r in A] == [key(r) for r in B] and len(A) == 24
+    for a, b in zip(A, B):
+        assert a.region == b.region and np.array_equal(a.candidates, b.candidates)
 
 
 @pytest.mark.parametrize("rows,cols,off_dst,off_src", [(3, 9001, 0, 0), (5, 4096, 4, 8),
