@@ -63,6 +63,7 @@ class Result:
     arrival: float
     done: float
     total: int                 # candidates found in the searched window (before the region cut)
+    truncated: bool = False    # the window found more than cand_cap: `candidates` is a prefix
 
     @property
     def latency(self) -> float:
@@ -231,11 +232,11 @@ class StreamServer:
             b.busy = False
             r0, r1 = grp[0].region[0], grp[-1].region[1]
             total = int(counts[i]) if r1 > r0 else 0
-            if total > self.cand_cap:
-                raise RuntimeError(f"beam {grp[0].beam} blocks {grp[0].index}..{grp[-1].index}: "
-                                   f"{total} candidates exceed the capacity {self.cand_cap}")
-            nb = total * spd.CANDIDATE_DTYPE.itemsize
-            if total > self.cand_prefix:
+            # a window with more than cand_cap candidates holds the first cand_cap of them in
+            # (level, dm, start) order, so each of its blocks gets a prefix of its own list
+            kept = min(total, self.cand_cap)
+            nb = kept * spd.CANDIDATE_DTYPE.itemsize
+            if kept > self.cand_prefix:
                 # more than the prefix copied with the batch: fetch the rest now (the batch is done)
                 pre = self.cand_prefix * spd.CANDIDATE_DTYPE.itemsize
                 s.cand_host[i, pre: nb].copy_(s.cand[i, pre: nb])
@@ -243,7 +244,7 @@ class StreamServer:
             for r in grp:
                 keep = (c["start"] >= r.region[0]) & (c["start"] < r.region[1])
                 self.results.append(Result(r.beam, r.index, r.region, c[keep].copy(), r.arrival,
-                                           now, total))
+                                           now, total, total > kept))
         if s.ws_off is not None:
             self.arena.free(s.ws_off)
         s.groups, s.windows, s.busy, s.ws_off, s.ws_bytes = [], [], False, None, 0
