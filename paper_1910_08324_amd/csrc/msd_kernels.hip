@@ -4,7 +4,8 @@
 //
 // A pass reads the row once and serves every level at the same time.  The row streams through
 // in tiles of 1024 samples, one float4 per thread; inside a tile the decimated values of levels
-// 1..8 are formed in registers (levels 1, 2 within a thread, 3..8 by pairwise sums across lanes)
+// 1..8 are formed in registers (levels 1, 2 within a thread, 3..8 by pairwise sums across lanes,
+// moved by DPP row shifts and readlane rather than through LDS)
 // and each lane accumulates the values it holds.  Values of levels 9 and up (at most 1/256 of the
 // samples) are formed once, in the first pass, into the workspace, and later passes read them
 // from there.  Per level, each thread keeps a count and the sums of (value - shift) and of its
@@ -16,6 +17,8 @@
 
 #include <math.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "spd.h"
 #include "spd_msd.h"
@@ -112,6 +115,48 @@ __device__ __forceinline__ void take(Acc &a, const Level &L, bool first, bool va
     a.s2 = fma(e, e, a.s2);
 }
 
+// v of lane l + 2^(K-3), for the lanes that are multiples of 2^(K-2) (other lanes get values
+// that are never used).  Within a row of 16 lanes a DPP row shift moves the value in registers;
+// across rows the two (or one) values needed are read out with readlane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int K>
+__device__ __forceinline__ double from_lane_above(double v, int lane) {
+    constexpr int span = 1 << (K - 3);
+    if constexpr (span <= 8) {
+        return dpp_f64<0x100 + span>(v);                // row_shl:span (lane l reads l + span)
+    } else if constexpr (span == 16) {
+        const double a = readlane_f64(v, 16), b = readlane_f64(v, 48);
+        return lane < 32 ? a : b;
+    } else {
+        return readlane_f64(v, 32);
+    }
+}
+
+// one step of the cross-lane cascade: level K from pairs of level K-1 values; each holder lane
+// (a multiple of 2^(K-2)) parks its value in the wave's slot of level K (NaN past the data;
+// in a FULL tile every value of levels 3..8 lies inside it)
+template <int K, bool FULL>
+__device__ __forceinline__ void level_step(double &v, double *slots, int lane, int s, int n) {
+    constexpr int kSlotK = K == 3 ? 0 : K == 4 ? 32 : K == 5 ? 48 : K == 6 ? 56 : K == 7 ? 60 : 62;
+    v = v + from_lane_above<K>(v, lane);
+    if ((lane & ((2 << (K - 3)) - 1)) == 0)
+        slots[kSlotK + (lane >> (K - 2))] = (FULL || s + (1 << K) <= n) ? v : __builtin_nan("");
+}
+
 __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
     __shared__ Part sh[4];
     __shared__ Level lv[SPD_MAX_LEVELS];
@@ -132,7 +177,6 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
     const bool vec = (((uintptr_t)xr) & 15) == 0;
     // a tile gives each wave 32 + 16 + 8 + 4 + 2 + 1 values of levels 3..8: lanes 0..31 take
     // level 3, 32..47 level 4, 48..55 level 5, 56..59 level 6, 60..61 level 7, 62 level 8
-    constexpr int kSlot[kRegLevels] = {0, 0, 0, 0, 32, 48, 56, 60, 62};
     const int my_k = lane < 32 ? 3 : lane < 48 ? 4 : lane < 56 ? 5 : lane < 60 ? 6 : lane < 62 ? 7
                                                                                    : lane < 63 ? 8 : kRegLevels;
     double *slots = slot_buf[wave];
@@ -193,36 +237,36 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
         };
         float4 nxt = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (read_row) fetch(0, nxt);
-        for (int tile = 0; read_row && tile < n_tiles; ++tile) {
-            const float4 cur = nxt;
-            if (tile + 1 < n_tiles) fetch(tile + 1, nxt);        // in flight while this tile computes
+        // one tile; FULL: every sample of the tile is inside the data (all tiles but the last),
+        // so the per-value validity tests fold away
+        auto tile_body = [&](auto full_tag, int tile, float4 cur) {
+            constexpr bool FULL = decltype(full_tag)::value;
             const int s = tile * kTile + 4 * tid;                // first sample of this thread
             const double v0[4] = {(double)cur.x, (double)cur.y, (double)cur.z, (double)cur.w};
             if (on0)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) take(a0, L0, first, s + q < n, v0[q]);
+                for (int q = 0; q < 4; ++q) take(a0, L0, first, FULL || s + q < n, v0[q]);
             // levels 1, 2 within the thread
             const double v1a = v0[0] + v0[1], v1b = v0[2] + v0[3];
             if (on1) {
-                take(a1, L1, first, s + 2 <= n, v1a);
-                take(a1, L1, first, s + 4 <= n, v1b);
+                take(a1, L1, first, FULL || s + 2 <= n, v1a);
+                take(a1, L1, first, FULL || s + 4 <= n, v1b);
             }
             double v = v1a + v1b;
-            if (on2) take(a2, L2, first, s + 4 <= n, v);
+            if (on2) take(a2, L2, first, FULL || s + 4 <= n, v);
             // levels 3..8 across lanes: after step k, lane l holds the value of level k that starts
             // at its own samples when l is a multiple of 2^(k-2); holders park their values in the
-            // wave's 64 slots (level k at slots kSlot[k] .., one per holder, NaN past the data), and
+            // wave's 64 slots (level k from slot 64 - 2^(9-k), one per holder, NaN past the data), and
             // every lane then takes the one value of its own level in its slot
-#pragma unroll
-            for (int k = 3; k < kRegLevels; ++k) {
-                const int span = 1 << (k - 3);
-                v = v + __shfl_down(v, span);
-                if ((lane & ((span << 1) - 1)) == 0)
-                    slots[kSlot[k] + (lane >> (k - 2))] = s + (1 << k) <= n ? v : __builtin_nan("");
-            }
+            level_step<3, FULL>(v, slots, lane, s, n);
+            level_step<4, FULL>(v, slots, lane, s, n);
+            level_step<5, FULL>(v, slots, lane, s, n);
+            level_step<6, FULL>(v, slots, lane, s, n);
+            level_step<7, FULL>(v, slots, lane, s, n);
+            level_step<8, FULL>(v, slots, lane, s, n);
             if (onm) {
                 const double mv = slots[lane];                   // written by this wave above
-                take(am, Lm, first, !__builtin_isnan(mv), mv);
+                take(am, Lm, first, FULL || !__builtin_isnan(mv), mv);
             }
             // levels 9 and 10 (and the level-10 values the higher levels are built from): the
             // first pass writes them to the workspace
@@ -239,6 +283,14 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
                 }
                 __syncthreads();
             }
+        };
+        for (int tile = 0; read_row && tile < n_tiles; ++tile) {
+            const float4 cur = nxt;
+            if (tile + 1 < n_tiles) fetch(tile + 1, nxt);        // in flight while this tile computes
+            if ((tile + 1) * kTile <= n)                         // uniform over the work-group
+                tile_body(std::true_type{}, tile, cur);
+            else
+                tile_body(std::false_type{}, tile, cur);
         }
         if (first && K > 11) {
             // levels 11.. from pairs of the level below, all in the workspace
