@@ -11,7 +11,8 @@
 // from there.  Per level, each thread keeps a count and the sums of (value - shift) and of its
 // square, with the shift the level's current mean estimate; after the pass the threads' partial
 // statistics (count, mean, sum of squared deviations) are merged pairwise with Chan, Golub &
-// LeVeque's formula in a fixed order.  Levels converge independently; the row's passes stop
+// LeVeque's formula in a fixed order.  Levels 0..2, which every lane serves, count their kept
+// values per wave instead, and their lanes' sums around the common shift are totalled directly.  Levels converge independently; the row's passes stop
 // when every level has.
 #include <hip/hip_runtime.h>
 
@@ -61,6 +62,24 @@ __device__ Part block_merge(Part p, Part *sh) {
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = p;
     __syncthreads();
     return merge(merge(sh[0], sh[1]), merge(sh[2], sh[3]));
+}
+
+// totals over the work-group of per-thread (count, sum, sum of squares) in a fixed order:
+// butterflies inside each wave (a + b == b + a, so the lanes agree), then the four waves in order
+__device__ Part block_sums(Part p, Part *sh) {
+    for (int o = 1; o < 64; o <<= 1) {
+        p.n += __shfl_xor(p.n, o);
+        p.mean += __shfl_xor(p.mean, o);
+        p.m2 += __shfl_xor(p.m2, o);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = p;
+    __syncthreads();
+    Part t;
+    t.n = (sh[0].n + sh[1].n) + (sh[2].n + sh[3].n);
+    t.mean = (sh[0].mean + sh[1].mean) + (sh[2].mean + sh[3].mean);
+    t.m2 = (sh[0].m2 + sh[1].m2) + (sh[2].m2 + sh[3].m2);
+    return t;
 }
 
 // a thread's running sums of one level: count, sum and sum of squares of (value - shift)
@@ -157,6 +176,32 @@ __device__ __forceinline__ void level_step(double &v, double *slots, int lane, i
         slots[kSlotK + (lane >> (K - 2))] = (FULL || s + (1 << K) <= n) ? v : __builtin_nan("");
 }
 
+// take for a level every lane of the wave serves: the count of kept values is kept per wave
+// (a ballot's population count, on the scalar unit) instead of per lane
+__device__ __forceinline__ void take_w(Acc &a, uint32_t &nw, const Level &L, bool first,
+                                       bool valid, double v) {
+    const double d = v - L.shift;
+    const bool ok = valid && (first || fabs(d) <= L.lim);
+    const double e = ok ? d : 0.0;           // (d may be NaN for a value past the data)
+    nw += (uint32_t)__popcll(__ballot(ok));
+    a.s1 += e;
+    a.s2 = fma(e, e, a.s2);
+}
+
+// statistics of a level all of whose values share one shift: the work-group's totals of the
+// lanes' sums and the waves' counts give the mean and the sum of squared deviations
+__device__ __forceinline__ Part wave_counted_part(const Acc &a, uint32_t nw, double shift, Part *sh) {
+    Part p = {(threadIdx.x & 63) == 0 ? (double)nw : 0.0, a.s1, a.s2};
+    const Part t = block_sums(p, sh);
+    Part u = {0.0, 0.0, 0.0};
+    if (t.n > 0.0) {
+        u.n = t.n;
+        u.mean = shift + t.mean / t.n;
+        u.m2 = fmax(0.0, t.m2 - t.mean * (t.mean / t.n));
+    }
+    return u;
+}
+
 __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
     __shared__ Part sh[4];
     __shared__ Level lv[SPD_MAX_LEVELS];
@@ -211,6 +256,7 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
         bool read_row = first;
         for (int k = 0; k < kreg; ++k) read_row = read_row || lv[k].active;
         Acc a0, a1, a2, am;                      // levels 0, 1, 2 and this lane's level of 3..8
+        uint32_t n0w = 0, n1w = 0, n2w = 0;      // the wave's kept counts of levels 0, 1, 2
         acc_reset(a0);
         acc_reset(a1);
         acc_reset(a2);
@@ -245,15 +291,15 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
             const double v0[4] = {(double)cur.x, (double)cur.y, (double)cur.z, (double)cur.w};
             if (on0)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) take(a0, L0, first, FULL || s + q < n, v0[q]);
+                for (int q = 0; q < 4; ++q) take_w(a0, n0w, L0, first, FULL || s + q < n, v0[q]);
             // levels 1, 2 within the thread
             const double v1a = v0[0] + v0[1], v1b = v0[2] + v0[3];
             if (on1) {
-                take(a1, L1, first, FULL || s + 2 <= n, v1a);
-                take(a1, L1, first, FULL || s + 4 <= n, v1b);
+                take_w(a1, n1w, L1, first, FULL || s + 2 <= n, v1a);
+                take_w(a1, n1w, L1, first, FULL || s + 4 <= n, v1b);
             }
             double v = v1a + v1b;
-            if (on2) take(a2, L2, first, FULL || s + 4 <= n, v);
+            if (on2) take_w(a2, n2w, L2, first, FULL || s + 4 <= n, v);
             // levels 3..8 across lanes: after step k, lane l holds the value of level k that starts
             // at its own samples when l is a multiple of 2^(k-2); holders park their values in the
             // wave's 64 slots (level k from slot 64 - 2^(9-k), one per holder, NaN past the data), and
@@ -306,8 +352,7 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
 
         // merge the pass's statistics and update every level still being refined (the decision
         // to skip a level is uniform across the work-group)
-        auto update = [&](int k, Part p) {
-            const Part u = block_merge(p, sh);
+        auto update_merged = [&](int k, const Part u) {
             if (tid == 0) {
                 Level &S = lv[k];
                 if (first) {
@@ -329,9 +374,10 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
             }
             __syncthreads();
         };
-        if (K > 0 && (first || lv[0].active)) update(0, acc_part(a0, lv[0].shift));
-        if (K > 1 && (first || lv[1].active)) update(1, acc_part(a1, lv[1].shift));
-        if (K > 2 && (first || lv[2].active)) update(2, acc_part(a2, lv[2].shift));
+        auto update = [&](int k, Part p) { update_merged(k, block_merge(p, sh)); };
+        if (K > 0 && (first || lv[0].active)) update_merged(0, wave_counted_part(a0, n0w, lv[0].shift, sh));
+        if (K > 1 && (first || lv[1].active)) update_merged(1, wave_counted_part(a1, n1w, lv[1].shift, sh));
+        if (K > 2 && (first || lv[2].active)) update_merged(2, wave_counted_part(a2, n2w, lv[2].shift, sh));
         for (int k = 3; k < kreg; ++k) {
             if (first || lv[k].active) {
                 Part p = {0.0, 0.0, 0.0};
