@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--proposal-eval", type=int, default=8192, help="held-out evaluation tiles")
     ap.add_argument("--proposal-batch", type=int, default=256)
     ap.add_argument("--no-msd", action="store_true", help="skip the noise-statistics section")
+    ap.add_argument("--msd-probe", action="store_true",
+                    help="only run the noise statistics of the beam a few times (for counter runs)")
     ap.add_argument("--msd-tau", type=float, default=3.0)
     ap.add_argument("--msd-iter", type=int, default=10)
     ap.add_argument("--batch-beams", type=int, default=32,
@@ -247,6 +249,17 @@ def main():
         return (spd.Config(method, w.l_end, threshold=w.threshold, segment=c.segment,
                            step_levels=c.step_levels),
                 {"segment": c.segment, "step_levels": c.step_levels, "shapes": len(c.measured)})
+
+    if args.msd_probe:
+        from paper_1910_08324_amd import msd as M
+        levels = int(w.l_end).bit_length()
+        for _ in range(3):
+            out = M.msd(x, levels, tau=args.msd_tau, max_iter=args.msd_iter, with_passes=True)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "msd", "dispatches": 3, "levels": levels, "tau": args.msd_tau,
+                          "max_iter": args.msd_iter, "n_dm": w.n_dm, "n": w.n,
+                          "passes_total": int(out[4].to(torch.int64).sum().item())}), flush=True)
+        return
 
     cfg, tuned = config_for(args.method)
     run = spd.Runner(x, mu, sg, cfg, cand_cap=1 << 22)
@@ -601,8 +614,11 @@ def msd_section(args, dev, x, w) -> dict:
            "dm_samples_per_s": w.n_dm * w.n / (ms * 1e-3),
            "passes_mean": round(float(passes.mean().item()), 3),
            "passes_max": int(passes.max().item()),
-           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+           # the sample reads against HBM; the kernel itself is bound by FP64 VALU issue (its SQ
+           # counters on this beam, profiles/msd_ska_beam_counters.txt)
+           "roofline": {"bound": "alu", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "basis": "sample reads x passes against HBM; FP64 VALU issue bounds it",
                         "algorithmic_bytes": nbytes, "kernel": "spdm::msd_kernel"}}
     log(f"[bench] msd: {ms:.3f} ms for {w.n_dm} x {w.n}, {levels} levels, {res['passes_mean']} "
         f"passes per row on average: {gbs:.0f} GB/s of sample reads ({gbs / HBM_PEAK_GBS:.3f} of HBM)")
