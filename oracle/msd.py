@@ -19,8 +19,8 @@ Readings taken here (the section gives no formulas):
     two (rho = 1 for white noise, so the white-noise scaling of Section 2.1 is the special case);
     above the last level rho stays at the last level's value.
 
-Everything here is FP64 with plain two-pass formulas (the GPU uses Chan et al.'s pairwise
-combination; the two must agree to rounding).
+Everything here is FP64 with plain two-pass formulas (the GPU sums around a running shift and
+combines partial statistics pairwise after Chan et al.; the two must agree to rounding).
 
 parity: pinned by tests/test_oracle_msd.py (numpy std, closed forms, hand-worked rejection).
 """
