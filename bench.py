@@ -438,8 +438,14 @@ def main():
             oplanes.planes(blk, zeros, ones, lv)
             spent += time.perf_counter() - ta
             done_rows += 64
+        cpu_model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": done_rows * w.n / spent, "unit": "DM·samples/s",
-               "cores": oplanes.threads(), "kind": "oracle",
+               "cores": oplanes.threads(), "cpu_model": cpu_model, "kind": "oracle",
                "sample": f"{done_rows} of {w.n_dm} DM rows x {w.n} samples, {args.method} planes "
                          f"(FP64 oracle, {spent:.1f} s)"}
         log(f"[bench] cpu oracle: {cpu['value']:.3e} DM*samples/s on {cpu['cores']} threads")
