@@ -87,7 +87,20 @@ def launch_kernel_name(method: str, info, i: int) -> str:
         group = 16 if int(info.max_width) <= 4096 else 64          # widths per max-only group
         return f"spd::exh_kernel<true, {multi}, {group}>"
     first = "true" if info.launch_first_level[i] == 0 else "false"
-    return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}, false>"
+    return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}, false, {step_threads(method, info, i)}>"
+
+
+def step_threads(method: str, info, i: int) -> int:
+    """Work-group size of cascade launch i: the library runs IG(1) tiles of at most 3072 units
+    on 128 threads, everything else on 256.  Launches after the first use a tile no longer than
+    the rows' slots at their first level need (a multiple of 256)."""
+    if FAMILY.get(method, 0) != 1:
+        return 256
+    T = int(info.segment)
+    if i > 0:
+        slots = -(-int(info.plane_slots[0]) // (1 << int(info.launch_first_level[i])))
+        T = min(T, max(256, -(-slots // 256) * 256))
+    return 128 if T <= 3072 else 256
 
 
 def launch_valu_ops(method: str, cfg, info, i: int, n_dm: int, n_in: int) -> float:
@@ -147,9 +160,14 @@ def read_traffic(method: str, kernel: str, shape=None):
             if ":" in line and not line.startswith("#") and "|" not in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash() or vals.get("method") != method:
         return None
-    if vals.get("method") != method or vals.get("kernel") != kernel:
+    if shape is not None and vals.get(f"kernel@{shape[0]}/{shape[1]}") == kernel:
+        try:                                # counters taken at this launch shape
+            return float(vals[f"hbm_bytes_per_launch@{shape[0]}/{shape[1]}"])
+        except (KeyError, ValueError):
+            return None
+    if vals.get("kernel") != kernel:
         return None
     if (shape is not None and
             (vals.get("segment") != str(shape[0]) or vals.get("step_levels") != str(shape[1]))):

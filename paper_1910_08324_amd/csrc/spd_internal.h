@@ -12,6 +12,8 @@ constexpr int kMaxLevels = SPD_MAX_LEVELS;
 constexpr int kMaxLevelWidths = SPD_MAX_LEVEL_WIDTHS;
 constexpr int kStepMaxLevels = 6;     // levels handled by one launch of the cascade kernel
 constexpr int kStepThreads = 256;     // threads per tile work-group
+constexpr int kSmallStepThreads = 128; // threads per IG(1) work-group on short tiles
+constexpr int kSmallTileMax = 3072;    // longest tile (units) run on kSmallStepThreads
 constexpr int kGroup = 4;             // consecutive slots evaluated together by one thread
 constexpr int kExhSlots = 256;        // output slots per exhaustive work item (64 lanes x 4)
 constexpr int kExhBlock = 512;        // widths per LDS window refill in the exhaustive kernel

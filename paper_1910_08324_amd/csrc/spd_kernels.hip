@@ -67,9 +67,10 @@ __global__ void evalmask_kernel(const MaskArgs A) {
 // ----------------------------------------------------------------------------------------
 // BoxDIT / IGRID cascade: one launch per step of up to kStepMaxLevels levels.
 //
-// Work-group = (DM row d, tile t) of 256 threads.  The tile covers T units of the step's
-// input series (the normalised samples in the first step, the decimated series y_{k0}
-// afterwards) plus the halo its widest boxcars reach.  The whole tile lives in LDS:
+// Work-group = (DM row d, tile t) of NTH threads (256; 128 for short IG(1) tiles).  The tile
+// covers T units of the step's input series (the normalised samples in the first step, the
+// decimated series y_{k0} afterwards) plus the halo its widest boxcars reach.  The whole tile
+// lives in LDS:
 //   1. load the window (coalesced float4), normalising z = (x - mu) / sigma in the first step;
 //   2. form the decimated levels in place, one pass and one barrier per level;
 //   3. evaluate every level's width set at every slot of the tile, 4 consecutive slots per
@@ -253,7 +254,7 @@ struct TabGeom {
 
 // One tile (DM row d, tile `tile`) of a cascade launch.  A holds what every beam of the launch
 // shares (levels, width patterns, tile length); G the beam's buffers and sizes.
-template <bool FIRST, int FAM, bool RHO, class G>
+template <bool FIRST, int FAM, bool RHO, int NTH, class G>
 __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const int d,
                                           const int tile, float *lds, uint32_t *st_cnt) {
     const int tid = threadIdx.x;
@@ -263,7 +264,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         // this row's 1/sigma(L) relative to 1/(sqrt(L) sigma): scale[j][u-1] = rtab[j][u-1] / rho(L)
         const float *rr = A.rho + (int64_t)d * A.ld_rho;
         float *sc = lds + A.lds_sc;
-        for (int i = tid; i < A.J * kMaxLevelWidths; i += kStepThreads) {
+        for (int i = tid; i < A.J * kMaxLevelWidths; i += NTH) {
             const int j = i / kMaxLevelWidths, u = i - j * kMaxLevelWidths + 1;
             if (u <= A.lv[j].umax) {
                 const double L = (double)A.lv[j].base + ldexp((double)u, A.lv[j].k);
@@ -285,7 +286,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         const int N0 = A.lv[0].n_units;
         float *y0 = lds + A.lv[0].lds_y;
         const int64_t len = V.in_len();
-        for (int i = tid * 4; i < N0; i += kStepThreads * 4) {
+        for (int i = tid * 4; i < N0; i += NTH * 4) {
             const int64_t r = u0 + i;
             float4 v;
             if (V.vec_ok() && r + 3 < len) {
@@ -310,7 +311,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         if (!FIRST && A.carry && V.cin()) {
             const float *cr = V.cin() + (int64_t)d * V.ld_cin();
             float *c0 = lds + A.lv[0].lds_c;
-            for (int i = tid; i < T; i += kStepThreads) {
+            for (int i = tid; i < T; i += NTH) {
                 const int64_t m = u0 + i;
                 c0[i] = (m < V.slots(0)) ? cr[m] : 0.0f;
             }
@@ -319,7 +320,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
     lds_barrier();
 
     // ---- 2+3. cascade fused with the width sets.  Level j is evaluated in batches of
-    // kStepThreads groups; each group also forms its two units of level j+1 (and, for BoxDIT,
+    // NTH groups (the work-group size); each group also forms its two units of level j+1 (and, for BoxDIT,
     // its two carried prefixes) in registers.  After a barrier that ends the batch's reads they
     // are written in place: unit n of level j+1 goes to index n of the same buffer, below every
     // unit of level j a later batch still reads (and likewise for the carries).  The units of
@@ -351,7 +352,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         uint16_t *rowW = V.W() + V.plane_off(j) + (int64_t)d * V.pitch(j);
         // a group is "fast" when the widest boxcar of its last slot ends inside the data
         const int64_t fast_lim = (int64_t)V.n_in() - base - ((int64_t)umax << k);
-        for (int gb = 0; gb < ngroups; gb += kStepThreads) {
+        for (int gb = 0; gb < ngroups; gb += NTH) {
             const int g = gb + tid;
             const int m0 = g * kGroup;
             const int ma = ms0 + m0;
@@ -462,7 +463,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         }
         if (form_next) {
             // halo units of level j+1: read at index >= S_j, written below it
-            for (int n = max(0, (Sj - cs1) >> 1) + tid; n < n_next; n += kStepThreads) {
+            for (int n = max(0, (Sj - cs1) >> 1) + tid; n < n_next; n += NTH) {
                 const float2 p = *reinterpret_cast<const float2 *>(yj + 2 * n + cs1);
                 ybuf[n] = p.x + p.y;
             }
@@ -474,7 +475,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
     if (A.has_out) {
         const float *yJ = lds + A.lv[0].lds_y;
         float *o = V.out() + (int64_t)d * V.ld_out() + (int64_t)tile * (T >> A.J);
-        for (int n = tid; n < (T >> A.J); n += kStepThreads) o[n] = yJ[n];
+        for (int n = tid; n < (T >> A.J); n += NTH) o[n] = yJ[n];
     }
     if (A.want_cand) {
         lds_barrier();
@@ -483,15 +484,15 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
 }
 
 
-// One launch for one beam: work-group = (DM row, tile).
-template <bool FIRST, int FAM, bool RHO>
-__global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel(const StepArgs A) {
+// One launch for one beam: work-group = (DM row, tile) of NTH threads.
+template <bool FIRST, int FAM, bool RHO, int NTH>
+__global__ __launch_bounds__(NTH, Fam<FAM>::WAVES) void step_kernel(const StepArgs A) {
     extern __shared__ float lds[];
     __shared__ uint32_t st_cnt[kStepMaxLevels];
     const int d = blockIdx.x / A.n_tiles;
     const int tile = blockIdx.x - d * A.n_tiles;
     if (d >= A.n_dm) return;
-    step_tile<FIRST, FAM, RHO>(A, ArgGeom{A}, d, tile, lds, st_cnt);
+    step_tile<FIRST, FAM, RHO, NTH>(A, ArgGeom{A}, d, tile, lds, st_cnt);
 }
 
 // One launch for many beams (same levels and tile length, any sizes): a persistent grid walks
@@ -511,7 +512,7 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel_bat
         const int d = (int)(local / V.n_tiles());
         const int tile = (int)(local - (int64_t)d * V.n_tiles());
         if (item != (int64_t)blockIdx.x) lds_barrier();   // the previous item is done with LDS
-        step_tile<FIRST, FAM, false>(B.s, V, d, tile, lds, st_cnt);
+        step_tile<FIRST, FAM, false, kStepThreads>(B.s, V, d, tile, lds, st_cnt);
     }
 }
 
@@ -1057,13 +1058,25 @@ int launch_evalmask(const MaskArgs &a, void *stream) {
     return (int)hipGetLastError();
 }
 
-template <bool FIRST, int FAM>
-static int launch_one(const StepArgs &a, int lds_bytes, hipStream_t st) {
+// IG(1) tiles of at most kSmallTileMax units run on work-groups of kSmallStepThreads: its light
+// width sets leave the launch bound by the plane writes, which go faster from more, smaller
+// work-groups (3.77 ms against 3.91 ms at the best tile of either size on the 4096 x 262144 beam;
+// the denser sets are faster on 256 threads).  Results do not depend on the work-group size.
+template <bool FIRST, int FAM, int NTH>
+static void launch_nth(const StepArgs &a, int lds_bytes, hipStream_t st) {
     const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_tiles));
     if (a.rho)
-        hipLaunchKernelGGL((step_kernel<FIRST, FAM, true>), grid, dim3(kStepThreads), lds_bytes, st, a);
+        hipLaunchKernelGGL((step_kernel<FIRST, FAM, true, NTH>), grid, dim3(NTH), lds_bytes, st, a);
     else
-        hipLaunchKernelGGL((step_kernel<FIRST, FAM, false>), grid, dim3(kStepThreads), lds_bytes, st, a);
+        hipLaunchKernelGGL((step_kernel<FIRST, FAM, false, NTH>), grid, dim3(NTH), lds_bytes, st, a);
+}
+
+template <bool FIRST, int FAM>
+static int launch_one(const StepArgs &a, int lds_bytes, hipStream_t st) {
+    if (FAM == 1 && a.T <= kSmallTileMax)
+        launch_nth<FIRST, FAM, kSmallStepThreads>(a, lds_bytes, st);
+    else
+        launch_nth<FIRST, FAM, kStepThreads>(a, lds_bytes, st);
     return (int)hipGetLastError();
 }
 
