@@ -125,11 +125,12 @@ def test_t0_offsets_candidate_starts(dev, method):
     assert np.array_equal(C1["snr"], C0["snr"]) and np.array_equal(C1["width"], C0["width"])
 
 
-@pytest.mark.parametrize("method,segs", [("ig1", [256, 1024, 2048]), ("bd16", [1024, 2048]),
+@pytest.mark.parametrize("method,segs", [("ig1", [256, 1024, 2048, 3072, 4096, 6144]), ("bd16", [1024, 2048]),
                                          ("ig3", [512, 3072]), ("bd32", [1024, 2048]),
                                          ("exh", [256, 512, 1024])])
 def test_tile_invariance_bitwise(dev, method, segs):
-    """Results do not depend on how time is split into work items (bit for bit)."""
+    """Results do not depend on how time is split into work items (bit for bit); for IG(1) the
+    tiles of at most 3072 units also run on 128-thread work-groups, the longer ones on 256."""
     from paper_1910_08324_amd import spd
     x, mu, sg = make_input(3, 20011, 17, pulses=[synth.Pulse(1, 5000, 700, 25.0, "gauss")])
     outs = []
