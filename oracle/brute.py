@@ -3,6 +3,11 @@
 TEST INFRASTRUCTURE ONLY.  Same definitions as planes.c (Section 2 eqs. boxcar, SNR, SNRlong with
 the white-noise scaling; Section 3 eq. for Y^i and W^i), but every boxcar is summed afresh from
 the raw samples, with no prefix sums, so it checks the prefix-sum oracle on small cases.
+
+gap (the margin by which the best width beats the runner-up, which decides where the GPU's
+FP32 argmax must equal the FP64 one) is taken here from the sorted list of every valid width's
+SNR at the slot, not from a running best / second-best pair as in planes.c: the top value minus
+the second one, +inf with fewer than two valid widths.
 """
 from __future__ import annotations
 
@@ -28,16 +33,22 @@ def planes(x: np.ndarray, mean, sigma, levels: Sequence[Level], n_out: int | Non
         n_slots = -(-n_out // stride)
         Y = np.full((n_dm, n_slots), -np.inf)
         W = np.zeros((n_dm, n_slots), np.int32)
+        G = np.full((n_dm, n_slots), np.inf)
         for d in range(n_dm):
             row = x[d].astype(np.float64)
             for m in range(n_slots):
                 s = m * stride
+                vals = []
                 for L in ws:                       # ascending: strict '>' keeps the smaller width
                     if s + L > n_in:
                         continue
                     v = (row[s:s + L].sum() - L * mean[d]) / (math.sqrt(L) * sigma[d])
+                    vals.append(v)
                     if v > Y[d, m]:
                         Y[d, m] = v
                         W[d, m] = L
-        out.append({"k": k, "Y": Y, "W": W})
+                if len(vals) >= 2:
+                    top = sorted(vals, reverse=True)
+                    G[d, m] = top[0] - top[1]
+        out.append({"k": k, "Y": Y, "W": W, "gap": G})
     return out

@@ -144,24 +144,34 @@ def conv_weight_grad(dz, a) -> np.ndarray:
     return dW
 
 
-def forward(F, net: Net, bf16: bool = False) -> dict:
-    """F [rows][P][C_IN] (rows a multiple of TILE_ROWS) -> activations, scores, tile logits."""
+def _rounder(bf16: bool, rnd):
+    """The map applied where the GPU stores bfloat16: rnd if given, else bf16 rounding or none."""
+    if rnd is not None:
+        return rnd
+    return lambda a: _maybe(a, bf16)
+
+
+def forward(F, net: Net, bf16: bool = False, rnd=None) -> dict:
+    """F [rows][P][C_IN] (rows a multiple of TILE_ROWS) -> activations, scores, tile logits.
+    rnd: optional map applied at every bfloat16 store except the features (error_budget)."""
     F = np.asarray(F, dtype=np.float64)
     rows = F.shape[0]
     assert rows % TILE_ROWS == 0
+    R = _rounder(bf16, rnd)
     a0 = _maybe(F, bf16)
-    z1 = conv(a0, _maybe(net.W1, bf16), net.b1)
-    a1 = _maybe(np.maximum(z1, 0.0), bf16)
-    z2 = conv(a1, _maybe(net.W2, bf16), net.b2)
-    a2 = _maybe(np.maximum(z2, 0.0), bf16)
-    z3 = conv(a2, _maybe(net.W3, bf16), net.b3)
-    a3 = _maybe(np.maximum(z3, 0.0), bf16)
+    z1 = conv(a0, R(net.W1), net.b1)
+    a1 = R(np.maximum(z1, 0.0))
+    z2 = conv(a1, R(net.W2), net.b2)
+    a2 = R(np.maximum(z2, 0.0))
+    z3 = conv(a2, R(net.W3), net.b3)
+    a3 = R(np.maximum(z3, 0.0))
     s = a3 @ net.wh + net.bh                                  # [rows][P]
     st = s.reshape(rows // TILE_ROWS, TILE_ROWS * P)
     mx = st.max(axis=1, keepdims=True)
     lse = mx[:, 0] + np.log(np.exp(st - mx).sum(axis=1))
     logits = lse - math.log(TILE_ROWS * P)
-    return {"a0": a0, "a1": a1, "a2": a2, "a3": a3, "s": s, "lse": lse, "logits": logits}
+    return {"a0": a0, "a1": a1, "a2": a2, "a3": a3, "s": s, "lse": lse, "logits": logits,
+            "W": (R(net.W1), R(net.W2), R(net.W3))}
 
 
 def loss_value(logits, labels) -> float:
@@ -172,9 +182,12 @@ def loss_value(logits, labels) -> float:
     return float(np.mean(sp - y * lg))
 
 
-def backward(F, labels, net: Net, bf16: bool = False):
-    """(loss, grads as a Net) of the mean logistic loss over the tiles of F."""
-    fw = forward(F, net, bf16)
+def backward(F, labels, net: Net, bf16: bool = False, rnd=None, fw=None):
+    """(loss, grads as a Net) of the mean logistic loss over the tiles of F.  rnd: as for
+    forward; fw: forward(F, net, bf16, rnd) if already computed."""
+    R = _rounder(bf16, rnd)
+    if fw is None:
+        fw = forward(F, net, bf16, rnd)
     rows = fw["s"].shape[0]
     n_tiles = rows // TILE_ROWS
     y = np.asarray(labels, np.float64)
@@ -186,16 +199,52 @@ def backward(F, labels, net: Net, bf16: bool = False):
     g = Net(*(np.zeros_like(getattr(net, n)) for n in Net.NAMES[:-1]), 0.0)
     g.wh = np.einsum("rp,rpc->c", ds, fw["a3"])
     g.bh = float(ds.sum())
-    dz3 = _maybe(ds[:, :, None] * net.wh[None, None, :] * (fw["a3"] > 0), bf16)
+    W1, W2, W3 = fw["W"]                                  # the weights the forward pass used
+    dz3 = R(ds[:, :, None] * net.wh[None, None, :] * (fw["a3"] > 0))
     g.W3 = conv_weight_grad(dz3, fw["a2"])
     g.b3 = dz3.sum(axis=(0, 1))
-    dz2 = _maybe(conv_input_grad(dz3, _maybe(net.W3, bf16)) * (fw["a2"] > 0), bf16)
+    dz2 = R(conv_input_grad(dz3, W3) * (fw["a2"] > 0))
     g.W2 = conv_weight_grad(dz2, fw["a1"])
     g.b2 = dz2.sum(axis=(0, 1))
-    dz1 = _maybe(conv_input_grad(dz2, _maybe(net.W2, bf16)) * (fw["a1"] > 0), bf16)
+    dz1 = R(conv_input_grad(dz2, W2) * (fw["a1"] > 0))
     g.W1 = conv_weight_grad(dz1, fw["a0"])
     g.b1 = dz1.sum(axis=(0, 1))
     return loss, g
+
+
+# --------------------------------------------------------------------------- error budget
+U_BF16 = 2.0 ** -8       # unit roundoff of bfloat16 (8 significant bits, round to nearest)
+
+
+def error_budget(F, labels, net: Net, n: int = 16, k: float = 10.0, seed: int = 0) -> dict:
+    """Element-wise budget for |network with bfloat16 roundings - plain FP64 network| of the
+    tile logits and of every gradient.
+
+    Error model: a round-to-nearest bfloat16 store of x returns x (1 + e) with |e| <= U_BF16.
+    The budget runs the FP64 network n times with every rounding site the GPU has (the conv
+    weights, the activations a1..a3 and the pre-activation gradients dz1..dz3; the features are
+    the input and exact) replaced by x (1 + U_BF16 r), r uniform on [-1, 1] and independent per
+    element, and takes per element k times the root-mean-square deviation from the unperturbed
+    network.  Any one set of roundings (the GPU's, or this module's bf16 mode) is one draw of
+    that model, so it falls within a few RMS of the FP64 result.  Returns {'logits': [tiles],
+    'loss': float, and one array per name of Net.NAMES}."""
+    rng = np.random.default_rng(seed)
+    F = np.asarray(F, np.float64)
+    ref_fw = forward(F, net)
+    ref_loss, ref_g = backward(F, labels, net)
+    acc = {"logits": np.zeros_like(ref_fw["logits"]), "loss": 0.0}
+    for name in Net.NAMES:
+        acc[name] = np.zeros_like(np.asarray(getattr(ref_g, name), np.float64))
+    for _ in range(n):
+        rnd = lambda a: np.asarray(a, np.float64) * (1.0 + U_BF16 * rng.uniform(-1.0, 1.0, np.shape(a)))
+        fw = forward(F, net, rnd=rnd)
+        acc["logits"] += (fw["logits"] - ref_fw["logits"]) ** 2
+        loss, g = backward(F, labels, net, rnd=rnd, fw=fw)
+        acc["loss"] += (loss - ref_loss) ** 2
+        for name in Net.NAMES:
+            acc[name] += (np.asarray(getattr(g, name), np.float64) -
+                          np.asarray(getattr(ref_g, name), np.float64)) ** 2
+    return {name: k * np.sqrt(v / n) for name, v in acc.items()}
 
 
 # --------------------------------------------------------------------------- optimiser

@@ -30,3 +30,11 @@ def oracle_lib():
     from oracle import planes
     planes._load()
     return planes
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Report the largest GPU-versus-oracle SNR error seen, as a fraction of the tolerance."""
+    mod = sys.modules.get("tests.parity")
+    if mod is not None and mod.WORST["ratio"] > 0:
+        terminalreporter.write_line(
+            f"parity: largest SNR error {mod.WORST['ratio']:.3f} x tolerance ({mod.WORST['what']})")

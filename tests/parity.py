@@ -3,9 +3,12 @@
 SNR:   |Y_gpu - Y_ref| <= TOL * max(1, |Y_ref|); a slot with no valid width is -inf on both sides
        with width 0.
 Width: equal to the oracle's wherever the oracle's gap between the best and the runner-up width
-       exceeds twice the SNR tolerance; elsewhere (a near-tie that FP32 rounding may decide
-       either way) the GPU's width must be one whose exact SNR is within twice the tolerance of
-       the best.
+       exceeds the SNR tolerance; elsewhere (a near-tie that FP32 rounding may decide either
+       way) the GPU's width must be one whose exact SNR is within twice the tolerance of the
+       best.  A width decision can only flip when the FP32 errors of the two SNRs differ by more
+       than their gap, so the 1 x tolerance rule holds whenever every GPU value is within half
+       the tolerance of the oracle; the largest error-to-tolerance ratio seen is recorded in
+       WORST and printed at the end of the run, so that the margin is visible.
 Candidates: the GPU list must contain every candidate whose every decision (threshold and all
        neighbour comparisons) holds with margin, and may contain only candidates none of whose
        decisions is violated beyond the margin.  Matched candidates follow the SNR/width rules.
@@ -17,6 +20,9 @@ import numpy as np
 from oracle import peaks, planes as oplanes
 
 TOL = 1e-5
+
+# largest |Y_gpu - Y_ref| / tol_of(Y_ref) seen by check_values in this process, and where
+WORST = {"ratio": 0.0, "what": ""}
 
 
 def tol_of(y):
@@ -39,11 +45,15 @@ def check_values(Yg, Wg, Yr, Wr, Gr, x, mu, sg, rows, starts, n_in, what="", wid
     fin = ~inf_r
     err = np.abs(Yg[fin] - Yr[fin])
     t = tol_of(Yr[fin])
+    if err.size:
+        r = float((err / t).max())
+        if r > WORST["ratio"]:
+            WORST.update(ratio=r, what=what)
     bad = np.nonzero(err > t)[0]
     if len(bad):
         i = np.nonzero(fin)[0][bad[:5]]
         raise AssertionError(f"{what}: SNR off at {i}: gpu={Yg[i]} ref={Yr[i]} err={err[bad[:5]]}")
-    tie = fin & (np.asarray(Gr) <= 2 * tol_of(Yr))
+    tie = fin & (np.asarray(Gr) <= tol_of(Yr))
     strict = fin & ~tie
     bad = np.nonzero(strict & (Wg != Wr))[0]
     assert len(bad) == 0, f"{what}: width differs at {bad[:5]} gpu={Wg[bad[:5]]} ref={Wr[bad[:5]]}"
@@ -74,13 +84,16 @@ def check_planes(gpu_planes, ref_planes, x, mu, sg, n_in, what="", width_sigma=N
     return stats
 
 
-def check_candidates(cands, ref_planes, threshold, t0=0, rows=None, what=""):
+def check_candidates(cands, ref_planes, threshold, t0=0, rows=None, what="", start_end=None):
     """cands: structured array from the GPU.  rows: restrict the check to these DM rows (the
-    reference planes must then hold rows rows-1..rows+1, indexed by `row_index`)."""
+    reference planes must then hold rows rows-1..rows+1, indexed by `row_index`).
+    start_end: the GPU list covers only starts below it (the reference planes still cover the
+    whole series, so the neighbours of the last covered slots are known)."""
     got = {}
     for c in cands:
         key = (int(c["level"]), int(c["dm"]), int(c["start"]))
         assert key not in got, f"{what}: duplicate candidate {key}"
+        assert start_end is None or key[2] < start_end, f"{what}: candidate {key} past {start_end}"
         got[key] = (float(c["snr"]), int(c["width"]))
     keys = list(got.keys())
     assert keys == sorted(keys), f"{what}: candidates not in (level, dm, start) order"
@@ -91,6 +104,8 @@ def check_candidates(cands, ref_planes, threshold, t0=0, rows=None, what=""):
         d_idx, m_idx = np.nonzero(rob)
         for d, m in zip(d_idx.tolist(), m_idx.tolist()):
             key = (lev, d, t0 + (m << k))
+            if start_end is not None and key[2] >= start_end:
+                continue
             assert key in got, f"{what}: missing robust candidate {key} snr={r['Y'][d, m]}"
             n_robust += 1
         for (l2, d, st), (snr, w) in got.items():
@@ -100,6 +115,6 @@ def check_candidates(cands, ref_planes, threshold, t0=0, rows=None, what=""):
             assert pos[d, m], f"{what}: candidate {(l2, d, st)} snr={snr} is not a possible peak"
             yr = r["Y"][d, m]
             assert abs(snr - yr) <= tol_of(yr), f"{what}: candidate SNR {snr} vs {yr}"
-            if r["gap"][d, m] > 2 * tol_of(yr):
+            if r["gap"][d, m] > tol_of(yr):
                 assert w == r["W"][d, m], f"{what}: candidate width {w} vs {r['W'][d, m]}"
     return len(got), n_robust

@@ -103,7 +103,13 @@ def test_forward_matches_oracle(P):
     ref = op.forward(F, net, bf16=True)["logits"]
     say(f"  logits gpu {lg} oracle {ref}")
     # FP32 accumulation on the GPU vs FP64 here, same bfloat16 roundings: ~1e-6 observed
-    assert np.allclose(lg, ref, rtol=1e-4, atol=1e-4)
+    assert np.all(np.abs(lg - ref) <= 1e-4 * np.maximum(1.0, np.abs(ref)))
+    # against the plain FP64 network, within the bfloat16 rounding budget of every logit
+    y = np.zeros(tiles)
+    B = op.error_budget(F, y, net)
+    exact = op.forward(F, net)["logits"]
+    say(f"  vs FP64 network: |diff| {np.abs(lg - exact)} budget {B['logits']}")
+    assert np.all(np.abs(lg - exact) <= B["logits"])
 
 
 @pytest.mark.parametrize("tiles", [5, 40])
@@ -136,12 +142,26 @@ def test_backward_matches_oracle(P, seed):
     ref_loss, ref = op.backward(F, y, net, bf16=True)
     assert loss == pytest.approx(ref_loss, rel=1e-4, abs=1e-5)
     got = P.unpack(g)
+    # element by element against the oracle with the same bfloat16 roundings: FP32 against
+    # FP64 accumulation, plus the rare value that lands on the other side of a bfloat16
+    # rounding boundary (one bfloat16 step, 2^-7 relative, in one stored tensor element)
     for n in op.Net.NAMES:
         a = np.asarray(got[n], np.float64)
         b = np.asarray(getattr(ref, n), np.float64)
-        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
-        say(f"  {n}: relative error {err:.2e}")
-        assert err < 1e-3, n       # ~1e-6 .. 1e-5 observed
+        tol = 1e-3 * np.abs(b) + 1e-4 * np.abs(b).max()
+        ratio = float(np.max(np.abs(a - b) / np.maximum(tol, 1e-300)))
+        say(f"  {n}: worst element |gpu - oracle(bf16)| / tol = {ratio:.3f}")
+        assert np.all(np.abs(a - b) <= tol), n
+    # and against the plain FP64 network, within the bfloat16 rounding budget of each element
+    exact_loss, exact = op.backward(F, y, net)
+    B = op.error_budget(F, y, net)
+    assert abs(loss - exact_loss) <= B["loss"]
+    for n in op.Net.NAMES:
+        a = np.asarray(got[n], np.float64)
+        b = np.asarray(getattr(exact, n), np.float64)
+        ratio = float(np.max(np.abs(a - b) / np.maximum(B[n], 1e-300)))
+        say(f"  {n}: worst element |gpu - FP64| / budget = {ratio:.3f}")
+        assert np.all(np.abs(a - b) <= B[n]), n
     pad = g[P.OFF["W1"]:P.OFF["W1"] + 1280].reshape(32, 5, 8)[:, :, 5:]
     assert np.all(pad == 0) and np.all(g[P.OFF["bh"] + 1:] == 0)
 

@@ -251,3 +251,61 @@ def test_candidate_overflow_is_reported_in_band(S):
             assert np.array_equal(b.candidates, a.candidates[: len(b.candidates)])
         else:
             assert np.array_equal(a.candidates, b.candidates)
+
+
+@pytest.mark.parametrize("method", ["ig1", "bd16"])
+def test_served_candidates_match_oracle(S, method):
+    """Two beams of 6 DM rows served block by block (blocks of 256..2048 samples, interleaved,
+    several slots in flight), L_end 512: the candidates of every block's region are checked
+    against the FP64 oracle's planes and peak finder over the beam's whole concatenated stream
+    (Section 3 per-iteration output, Section 4.6 candidate selection), with the tolerance rules
+    of the offline parity tests."""
+    import synth
+    from oracle import planes as oplanes, widths as ow
+    from tests import parity
+    n_dm, l_end, thr = 6, 512, 4.5
+    rng = np.random.default_rng(17)
+    streams, mus, sgs = {}, {}, {}
+    for b in range(2):
+        sizes = [int(v) * 256 for v in rng.integers(1, 9, 16)]
+        n = sum(sizes)
+        mu = rng.uniform(-1, 1, n_dm).astype(np.float32)
+        sg = rng.uniform(0.5, 2.0, n_dm).astype(np.float32)
+        x = synth.noise_rows(n, 300 + b, range(n_dm))
+        pulses = [synth.Pulse(int(d), int(t), int(w), float(c))
+                  for d, t, w, c in zip(rng.integers(0, n_dm, 12), rng.integers(0, n - 600, 12),
+                                        rng.integers(1, 200, 12), rng.uniform(6, 30, 12))]
+        synth.inject(x, pulses)
+        x = x * sg[:, None] + mu[:, None]
+        streams[b] = (x.astype(np.float32), sizes)
+        mus[b], sgs[b] = mu, sg
+    srv = S.StreamServer(method=method, l_end=l_end, threshold=thr, max_block=2048, slots=2,
+                         max_beams_per_batch=2, coalesce=3)
+    blocks = {}
+    for b, (x, sizes) in streams.items():
+        srv.open_beam(b, n_dm, torch.from_numpy(mus[b]).cuda(), torch.from_numpy(sgs[b]).cuda())
+        edges = np.concatenate([[0], np.cumsum(sizes)])
+        blocks[b] = [torch.from_numpy(np.ascontiguousarray(x[:, a:e])).cuda()
+                     for a, e in zip(edges[:-1], edges[1:])]
+    for i in range(16):
+        for b in (0, 1):
+            srv.submit(b, blocks[b][i])
+            srv.poll()
+    srv.drain()
+    lv = ow.method_levels(method, l_end)
+    for b, (x, sizes) in streams.items():
+        res = sorted([r for r in srv.results if r.beam == b], key=lambda r: r.index)
+        assert [r.index for r in res] == list(range(16))
+        for a, c in zip(res, res[1:]):
+            assert a.region[1] == c.region[0]
+        r_end = res[-1].region[1]
+        assert r_end > sum(sizes) // 2
+        got = np.concatenate([r.candidates for r in res])
+        for r in res:
+            c = r.candidates
+            assert np.all((c["start"] >= r.region[0]) & (c["start"] < r.region[1]))
+        R = oplanes.planes(x, mus[b], sgs[b], lv)
+        n_got, n_rob = parity.check_candidates(got, R, thr, what=f"{method} beam {b}",
+                                               start_end=r_end)
+        say(f"  {method} beam {b}: region end {r_end}, {n_got} served, {n_rob} robust")
+        assert n_rob > 5

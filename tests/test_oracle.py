@@ -199,6 +199,39 @@ def test_prefix_oracle_matches_direct_sums(m):
             assert np.array_equal(a["W"][fin], b["W"][fin])
             assert np.array_equal(np.isfinite(a["Y"]), np.isfinite(b["Y"]))
             assert np.all(a["W"][~np.isfinite(a["Y"])] == 0)
+            # gap: runner-up margin, +inf where fewer than two widths are valid
+            assert np.array_equal(np.isinf(a["gap"]), np.isinf(b["gap"]))
+            g = np.isfinite(b["gap"])
+            np.testing.assert_allclose(a["gap"][g], b["gap"][g], rtol=0, atol=1e-10)
+            assert np.all(a["gap"][g] >= 0)
+
+
+@pytest.mark.parametrize("m", ["exh", "ig1", "bd8"])
+def test_gap_special_cases(m):
+    """gap of the oracle on inputs whose margins are known exactly: zero input ties every width
+    (gap 0, smallest width wins); a slot where exactly one width is valid has gap +inf; and a
+    lone spike of height h at the slot's start under widths L1 < L2 gives SNRs h / sqrt(L), so
+    the margin is h (1/sqrt(L1) - 1/sqrt(L2)) between the two narrowest valid widths."""
+    lv = widths.method_levels(m, 32)
+    n = 96
+    z = planes.planes(np.zeros((1, n), np.float32), 0.0, 1.0, lv)
+    for p, (k, ws) in zip(z, lv):
+        for mm in range(p["Y"].shape[1]):
+            valid = [w for w in ws if (mm << k) + w <= n]
+            if len(valid) >= 2:
+                assert p["gap"][0, mm] == 0.0 and p["W"][0, mm] == valid[0]
+            elif len(valid) == 1:
+                assert p["gap"][0, mm] == np.inf and p["W"][0, mm] == valid[0]
+            else:
+                assert p["gap"][0, mm] == np.inf and p["W"][0, mm] == 0
+    h = 3.0
+    x = np.zeros((1, n), np.float32)
+    x[0, 0] = h
+    k0, ws0 = lv[0]
+    p = planes.planes(x, 0.0, 1.0, lv)[0]
+    L1, L2 = ws0[0], ws0[1]
+    assert p["W"][0, 0] == L1
+    assert p["gap"][0, 0] == pytest.approx(h / math.sqrt(L1) - h / math.sqrt(L2), rel=1e-12)
 
 
 @pytest.mark.parametrize("m", ["exh", "ig1", "bd16"])

@@ -161,6 +161,34 @@ def test_bf16_mode_rounds_stored_tensors():
         assert np.abs(a - b).max() <= 0.05 * np.abs(b).max(), n
 
 
+def test_error_budget_bounds_bf16_rounding():
+    """The stochastic bfloat16 error model bounds a real set of roundings: this module's bf16
+    mode (round to nearest even at every store, an independent realisation) deviates from the
+    FP64 network by less than the budget at every logit and gradient element; the budget is
+    small against the values (so it is not vacuous), and a plausible mistake (a W2 gradient
+    with its tap order reversed, one W3 element off by 5%) exceeds it."""
+    F, net, y = small_case(seed=7)
+    F = op.round_bf16(F)
+    B = op.error_budget(F, y, net)
+    fb, f = op.forward(F, net, bf16=True), op.forward(F, net)
+    assert np.all(np.abs(fb["logits"] - f["logits"]) <= B["logits"])
+    assert np.all(B["logits"] < 0.05)
+    loss_b, gb = op.backward(F, y, net, bf16=True)
+    loss, g = op.backward(F, y, net)
+    assert abs(loss_b - loss) <= B["loss"]
+    for n in op.Net.NAMES:
+        a, b = np.asarray(getattr(gb, n)), np.asarray(getattr(g, n))
+        assert np.all(np.abs(a - b) <= B[n]), n
+        assert np.median(B[n] / np.maximum(np.abs(b), 1e-30)) < 0.5, n
+        assert np.max(B[n]) < 0.2 * np.abs(b).max(), n
+    bad = g.W2[:, ::-1, :]
+    assert np.any(np.abs(bad - g.W2) > B["W2"])
+    bad = g.W3.copy()
+    i = np.unravel_index(np.argmax(np.abs(g.W3)), g.W3.shape)
+    bad[i] *= 1.05
+    assert np.any(np.abs(bad - g.W3) > B["W3"])
+
+
 def test_adam_matches_torch():
     rng = np.random.default_rng(8)
     p0 = rng.standard_normal(20)
