@@ -64,13 +64,14 @@ def algorithmic_bytes(info, n_dm: int, n_in: int) -> int:
     return n_dm * n_in * 4 + n_dm * slots * 6
 
 
-def launch_bytes(info, i: int, n_dm: int) -> int:
+def launch_bytes(info, i: int, n_dm: int, planes: bool = True) -> int:
     """Algorithmic bytes of filter launch i: the floats it reads per row once (the samples, or the
     decimated series handed on by the previous launch), the plane slots of its levels once
-    (6 B each) and the floats it hands to the next launch once."""
+    (6 B each; none when only candidates are requested) and the floats it hands to the next
+    launch once."""
     b = n_dm * 4 * (int(info.launch_in_units[i]) + int(info.launch_out_units[i]))
     f, c = int(info.launch_first_level[i]), int(info.launch_levels[i])
-    if f >= 0:
+    if f >= 0 and planes:
         b += n_dm * 6 * sum(int(info.plane_slots[k]) for k in range(f, f + c))
     return b
 
@@ -79,7 +80,8 @@ FAMILY = {"ig1": 1, "ig2": 2, "ig3": 3, "bd8": 4, "bd16": 5, "bd32": 6, "dit": 7
 
 
 def launch_kernel_name(method: str, info, i: int) -> str:
-    """Kernel symbol of filter launch i, as rocprofv3 lists it."""
+    """Kernel symbol of filter launch i, as rocprofv3 lists it (the work-group size is the one the
+    library's planner reports for the launch)."""
     if method == "exh":
         if info.launch_first_level[i] < 0:
             return "spd::scales_kernel"
@@ -87,20 +89,7 @@ def launch_kernel_name(method: str, info, i: int) -> str:
         group = 16 if int(info.max_width) <= 4096 else 64          # widths per max-only group
         return f"spd::exh_kernel<true, {multi}, {group}>"
     first = "true" if info.launch_first_level[i] == 0 else "false"
-    return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}, false, {step_threads(method, info, i)}>"
-
-
-def step_threads(method: str, info, i: int) -> int:
-    """Work-group size of cascade launch i: the library runs IG(1) tiles of at most 3072 units
-    on 128 threads, everything else on 256.  Launches after the first use a tile no longer than
-    the rows' slots at their first level need (a multiple of 256)."""
-    if FAMILY.get(method, 0) != 1:
-        return 256
-    T = int(info.segment)
-    if i > 0:
-        slots = -(-int(info.plane_slots[0]) // (1 << int(info.launch_first_level[i])))
-        T = min(T, max(256, -(-slots // 256) * 256))
-    return 128 if T <= 3072 else 256
+    return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}, false, {int(info.launch_threads[i])}>"
 
 
 def launch_valu_ops(method: str, cfg, info, i: int, n_dm: int, n_in: int) -> float:
@@ -140,7 +129,7 @@ def dominant_entry(method: str, cfg, run, w, reps: int, lms=None) -> dict:
         lms = time_launches(run, reps)
     dom = max(range(len(lms)), key=lambda i: lms[i])
     sec = lms[dom] * 1e-3
-    gbs = launch_bytes(info, dom, w.n_dm) / sec / 1e9
+    gbs = launch_bytes(info, dom, w.n_dm, planes=cfg.planes) / sec / 1e9
     tops = launch_valu_ops(method, cfg, info, dom, w.n_dm, w.n) / sec / 1e12
     hf, vf = gbs / HBM_PEAK_GBS, tops / VALU_PEAK_TOPS
     return {"kernel": launch_kernel_name(method, info, dom), "ms": round(lms[dom], 4),
@@ -374,6 +363,9 @@ def main():
     del run
     torch.cuda.empty_cache()
 
+    # ---------------- the same search, candidates only (no planes stored) -------------------
+    conly = candidates_only_section(args, cfg, x, mu, sg, w, C)
+
     # ---------------- other methods, exhaustive --------------------------------------------
     methods = {args.method: {"ms": round(ms_step, 4), "rtf": round(rtf, 1),
                              "filter_ms": round(filt_ms, 4), "dominant": dom_main}}
@@ -516,6 +508,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "methods": methods,
+        "candidates_only": conly,
     }
     if "exh" in methods:
         out["rtf_exhaustive"] = methods["exh"]["rtf"]
@@ -532,6 +525,51 @@ def main():
     if prop is not None:
         out["proposal"] = prop
     print(json.dumps(out), flush=True)
+
+
+def candidates_only_section(args, cfg, x, mu, sg, w, C_planes) -> dict:
+    """The headline search with SPD_WRITE_CANDIDATES only: the cascade stores no planes and the
+    peak finder forms the slot values it tests again.  Its candidates must equal those of the
+    search that writes the planes (checked here on the beam)."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_1910_08324_amd import spd
+    c2 = dataclasses.replace(cfg, planes=False)
+    run = spd.Runner(x, mu, sg, c2, cand_cap=1 << 22)
+    for _ in range(args.warmup):
+        run.search()
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    t0 = time.perf_counter()
+    for i in range(K):
+        ev[i][0].record()
+        run.filter()
+        ev[i][1].record()
+        run.peaks()
+        ev[i][2].record()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / K
+    filt = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    peak = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    same = bool(np.array_equal(run.result.candidates_host(), C_planes))
+    dom = dominant_entry(args.method, c2, run, w, K)
+    info = run.info
+    in_bytes = sum(launch_bytes(info, i, w.n_dm, planes=False) for i in range(info.n_launches))
+    out = {"ms": round(ms, 4), "filter_ms": round(filt, 4), "peaks_ms": round(peak, 4),
+           "dm_samples_per_s": w.n_dm * w.n / (ms * 1e-3),
+           "rtf": round(w.n * T_SAMPLE / (ms * 1e-3), 1),
+           "algorithmic_bytes_per_dm_sample": round(in_bytes / (w.n_dm * w.n), 4),
+           "candidates_equal_planes_mode": same, "dominant": dom}
+    log(f"[bench] {args.method} candidates only: {ms:.3f} ms/step (filter {filt:.3f}, peaks "
+        f"{peak:.3f}), dominant {dom['kernel']} {dom['ms']} ms = {dom['hbm_frac']:.3f} of HBM; "
+        f"same candidates as planes mode: {same}")
+    del run
+    torch.cuda.empty_cache()
+    return out
 
 
 def sweep(dev) -> dict:

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SPD_ABI_VERSION 4
+#define SPD_ABI_VERSION 5
 
 /* Status codes. */
 #define SPD_OK          0
@@ -144,6 +144,9 @@ typedef struct {
     int64_t launch_in_units[SPD_MAX_LAUNCHES];    /* floats read per DM row (samples, or decimated
                                                      series and carried prefixes handed on)   */
     int64_t launch_out_units[SPD_MAX_LAUNCHES];   /* floats per DM row handed to the next launch */
+    int32_t launch_threads[SPD_MAX_LAUNCHES];     /* threads per work-group of each launch       */
+    int32_t launch_tile[SPD_MAX_LAUNCHES];        /* units of the launch's input per work-group
+                                                     (cascade launches; 0 for the others)     */
 } spd_plan_info;
 
 /*
@@ -222,6 +225,42 @@ int spd_filter_timed(const spd_params *params, const float *x, int64_t ld, int32
                      int32_t n_in, int32_t n_out, const float *mean, const float *sigma,
                      float *snr, uint16_t *width, void *workspace, int64_t workspace_bytes,
                      void *hip_stream, float *launch_ms, int32_t cap, int32_t *n_launches);
+
+/*
+ * Tile-gated search: the lossy search everywhere and the exhaustive set (Section 3.1, the ideal
+ * search the paper measures its losses against) only on flagged tiles of the DM x time block,
+ * as a tile proposal selects them (spd_proposal.h).
+ *
+ * spd_gated_plan: HOST *workspace_bytes for spd_search_gated with these sizes.
+ * spd_search_gated: on `hip_stream`,
+ *   1. the lossy search `lossy` (BoxDIT or IGRID, SPD_WRITE_CANDIDATES required; its planes to
+ *      snr/width with SPD_WRITE_PLANES, as for spd_search);
+ *   2. the exhaustive search `exh` (SPD_EXHAUSTIVE, SPD_WRITE_CANDIDATES required) at the slots
+ *      of flagged tiles only.  With SPD_WRITE_PLANES its level-0 plane goes to exh_snr/exh_width
+ *      (layout of spd_plan for `exh`); slots outside flagged tiles are left untouched.
+ *   Tiles: tile (r, c) holds DM rows [r tile_rows, (r+1) tile_rows) and output slots (samples)
+ *   [c tile_len, (c+1) tile_len); tile_flag is a DEVICE uint8 array
+ *   [ceil(n_dm / tile_rows)][ceil(n_out / tile_len)], nonzero = flagged.  tile_rows >= 1;
+ *   tile_len a multiple of 1024.
+ *   Candidates (cand, cand_cap, cand_count as for spd_search): first the lossy search's
+ *   candidates whose (dm, start - t0) lies in an unflagged tile, in (level, dm, start) order,
+ *   then the exhaustive search's candidates in flagged tiles in (dm, start) order (level 0).
+ *   The exhaustive candidates' 3x3 test sees only neighbours inside flagged tiles (the plane
+ *   exists only there); the lossy candidates' test sees the complete lossy planes.  Values and
+ *   widths are bitwise those of spd_search with the same parameters at the same slots.
+ *   Returns as spd_search (SPD_EINVAL also for the wrong method in either params or a bad tile
+ *   shape).
+ */
+int spd_gated_plan(const spd_params *lossy, const spd_params *exh, int32_t n_dm, int32_t n_in,
+                   int32_t n_out, int32_t tile_rows, int32_t tile_len, int64_t *workspace_bytes);
+
+int spd_search_gated(const spd_params *lossy, const spd_params *exh, const float *x, int64_t ld,
+                     int32_t n_dm, int32_t n_in, int32_t n_out, int64_t t0, const float *mean,
+                     const float *sigma, const uint8_t *tile_flag, int32_t tile_rows,
+                     int32_t tile_len, float *snr, uint16_t *width, float *exh_snr,
+                     uint16_t *exh_width, spd_candidate *cand, int64_t cand_cap,
+                     int64_t *cand_count, void *workspace, int64_t workspace_bytes,
+                     void *hip_stream);
 
 /* Human-readable text for a status code (static storage; includes the last HIP error text for
  * SPD_EHIP on this thread). */

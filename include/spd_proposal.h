@@ -121,6 +121,15 @@ int spd_tile_max(const float *snr, const spd_plan_info *info, int32_t n_dm, int3
 int spd_prop_labels(const float *exh_max, const float *lossy_max, int32_t n_tiles,
                     float threshold, float margin, float *labels, void *hip_stream);
 
+/*
+ * spd_prop_flags: the tile flag map of spd_search_gated (spd.h) from the logits of a grid of
+ * n_row_tiles x n_col_tiles tiles.  logits [n_col_tiles * n_row_tiles] hold tile (r, c) at
+ * c n_row_tiles + r (the order of spd_prop_features run on one column of tiles after another);
+ * flags [n_row_tiles][n_col_tiles] (uint8) get 1 where the logit is above logit_threshold.
+ */
+int spd_prop_flags(const float *logits, int32_t n_row_tiles, int32_t n_col_tiles,
+                   float logit_threshold, uint8_t *flags, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

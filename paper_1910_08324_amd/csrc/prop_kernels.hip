@@ -620,6 +620,16 @@ __global__ void labels_kernel(const float *e, const float *l, int32_t n, float t
     out[i] = (e[i] > thr && e[i] > prod) ? 1.0f : 0.0f;
 }
 
+// tile (r, c) of an n_row x n_col grid: logits in column order (c n_row + r, as the features of
+// one column of tiles after another give them), flags in row order (r n_col + c)
+__global__ void flags_kernel(const float *logits, int32_t n_row, int32_t n_col, float thr,
+                             uint8_t *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_row * n_col) return;
+    const int64_t r = i / n_col, c = i - r * n_col;
+    flags[i] = logits[c * n_row + r] > thr ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------------------
 // Fused inference: one work-group per row runs the three convolutions with the activations in
 // LDS (features 4.2 KB, two activation buffers of 21 KB), then the read-out; only the
@@ -1075,6 +1085,18 @@ int spd_prop_labels(const float *exh_max, const float *lossy_max, int32_t n_tile
     SPDP_LAUNCH(labels_kernel, dim3((n_tiles + 255) / 256), dim3(256), 0,
                 static_cast<hipStream_t>(hip_stream), exh_max, lossy_max, n_tiles, threshold, m,
                 labels);
+    return SPD_OK;
+}
+
+int spd_prop_flags(const float *logits, int32_t n_row_tiles, int32_t n_col_tiles,
+                   float logit_threshold, uint8_t *flags, void *hip_stream) {
+    if (!logits || !flags || n_row_tiles < 1 || n_col_tiles < 1 ||
+        (int64_t)n_row_tiles * n_col_tiles > INT32_MAX)
+        return SPD_EINVAL;
+    const int64_t n = (int64_t)n_row_tiles * n_col_tiles;
+    SPDP_LAUNCH(flags_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                static_cast<hipStream_t>(hip_stream), logits, n_row_tiles, n_col_tiles,
+                logit_threshold, flags);
     return SPD_OK;
 }
 

@@ -186,6 +186,7 @@ constexpr int kDefaultStepLevels = 4;
 // One launch of the cascade kernel: levels k0 .. k0+J-1 over tiles of T units of its input.
 struct StepPlan {
     int k0 = 0, J = 0, T = 0, tiles = 0, maxu = 8, lds_bytes = 0, lds_sc = 0;
+    int nth = spd::kStepThreads;   // threads per work-group of the single-beam launch
     bool has_out = false;
     int64_t in_len = 0;        // units of the input series per row
     int64_t out_len = 0;       // units handed to the next step per row
@@ -207,6 +208,7 @@ struct Layout {
     int tile_slots[kMaxLevels] = {0};
     int64_t off_scale = 0, off_mask = 0, off_cnt = 0, off_ent = 0, off_surv = 0, off_msk = 0;
     int64_t off_wtot = 0, off_woff = 0, off_Y = -1, off_W = -1;
+    int64_t off_rec = -1;     // records of the cascade steps (lossy, candidates only)
     int64_t scale_ld = 0;
 };
 
@@ -394,6 +396,11 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
                 }
             }
             st.in_len = in_len;
+            // IG(1) tiles of at most kSmallTileMax units run on kSmallStepThreads: its light width
+            // sets leave the launch bound by the plane writes, which go faster from more, smaller
+            // work-groups; the denser sets are faster on kStepThreads
+            st.nth = (s.fam == 1 && st.T <= spd::kSmallTileMax) ? spd::kSmallStepThreads
+                                                                  : spd::kStepThreads;
             const int64_t slots0 = I.plane_slots[k0];
             int64_t tiles = ceil_div(slots0, st.T);
             if (st.has_out) {
@@ -427,22 +434,25 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
         }
     }
     // the launches of the filter, in stream order
-    auto add_launch = [&](int first, int nlv, int64_t in_units, int64_t out_units) {
+    auto add_launch = [&](int first, int nlv, int64_t in_units, int64_t out_units, int nth,
+                          int tile) {
         const int i = I.n_launches++;
         I.launch_first_level[i] = first;
         I.launch_levels[i] = nlv;
         I.launch_in_units[i] = in_units;
         I.launch_out_units[i] = out_units;
+        I.launch_threads[i] = nth;
+        I.launch_tile[i] = tile;
     };
     if (lossy) {
         const int series = s.method == SPD_BOXDIT ? 2 : 1;   // decimated series (+ carried prefixes)
         for (const StepPlan &st : L->steps)
             add_launch(st.k0, st.J, st.k0 == 0 ? (int64_t)n_in : series * st.in_len,
-                       st.has_out ? series * st.out_len : 0);
+                       st.has_out ? series * st.out_len : 0, st.nth, st.T);
     } else {
-        add_launch(-1, 0, 0, 0);                                  // 1/sqrt(L) table
-        if (!s.dense) add_launch(-1, 0, 0, 0);                    // width mask
-        add_launch(0, 1, n_in, 0);
+        add_launch(-1, 0, 0, 0, 256, 0);                          // 1/sqrt(L) table
+        if (!s.dense) add_launch(-1, 0, 0, 0, 256, 0);            // width mask
+        add_launch(0, 1, n_in, 0, 64, 0);
     }
     if (I.n_launches > SPD_MAX_LAUNCHES) return SPD_EINVAL;
 
@@ -468,8 +478,15 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
     L->off_wtot = take((int64_t)L->n_waves * 8);
     L->off_woff = take((int64_t)L->n_waves * 8);
     if (!(p->flags & SPD_WRITE_PLANES)) {
-        L->off_Y = take(I.plane_elems * 4);
-        L->off_W = take(I.plane_elems * 2);
+        if (lossy) {
+            // candidates only: no planes anywhere; the peak finder forms the few slot values it
+            // reads again from each step's record
+            L->off_rec = take((int64_t)L->steps.size() * (int64_t)sizeof(spd::RecStep));
+        } else {
+            // the exhaustive search is bound by arithmetic: its planes go to the workspace
+            L->off_Y = take(I.plane_elems * 4);
+            L->off_W = take(I.plane_elems * 2);
+        }
     }
     I.workspace_bytes = ws;
     return SPD_OK;
@@ -483,6 +500,10 @@ int hip_fail(int err) {
 }
 
 }  // namespace
+
+namespace spd {
+int record_hip_error(int err) { return hip_fail(err); }
+}  // namespace spd
 
 extern "C" {
 
@@ -550,8 +571,8 @@ int prepare(const spd_params *params, int32_t n_dm, int32_t n_in, int32_t n_out,
     if ((uintptr_t)workspace & 255) return SPD_EALIGN;
     if (want_planes && (((uintptr_t)snr & 15) || ((uintptr_t)width & 7))) return SPD_EALIGN;
     P->ws = static_cast<char *>(workspace);
-    P->Y = want_planes ? snr : reinterpret_cast<float *>(P->ws + P->L.off_Y);
-    P->W = want_planes ? width : reinterpret_cast<uint16_t *>(P->ws + P->L.off_W);
+    P->Y = want_planes ? snr : P->L.off_Y >= 0 ? reinterpret_cast<float *>(P->ws + P->L.off_Y) : nullptr;
+    P->W = want_planes ? width : P->L.off_W >= 0 ? reinterpret_cast<uint16_t *>(P->ws + P->L.off_W) : nullptr;
     return SPD_OK;
 }
 
@@ -570,6 +591,9 @@ void fill_step_shared(const spd_params *params, const Search &s, const StepPlan 
     a->ld_rho = params->n_rho;
     a->n_rho = params->n_rho;
     a->lds_sc = st.lds_sc;
+    a->write_planes = (params->flags & SPD_WRITE_PLANES) != 0;
+    a->nth = st.nth;
+    a->rec = nullptr;
     for (int j = 0; j <= st.J && j <= spd::kStepMaxLevels; ++j) a->lv[j] = st.lv[j];
     std::memcpy(a->rtab, st.rtab, sizeof(a->rtab));
 }
@@ -590,9 +614,17 @@ struct LaunchMarks {
     }
 };
 
+// Tile gating of a search (spd_search_gated): the tile flag map and which tiles a pass keeps.
+struct Gate {
+    const uint8_t *flag = nullptr;   // [n_row_tiles][n_col_tiles]
+    int tile_rows = 0, tile_len = 0, n_col_tiles = 0;
+    int mode = 0;                    // peak finder: 1 = unflagged tiles, 2 = flagged tiles
+    const int64_t *base = nullptr;   // candidates written before this pass's list
+};
+
 int run_filter(const spd_params *params, const Prepared &P, const float *x, int64_t ld,
                int32_t n_dm, int32_t n_in, int32_t n_out, const float *mean, const float *sigma,
-               void *hip_stream, LaunchMarks *marks = nullptr) {
+               void *hip_stream, LaunchMarks *marks = nullptr, const Gate *gate = nullptr) {
     auto mark = [&]() { return marks ? marks->mark() : 0; };
     if (const int err = mark()) return hip_fail(err);
     const Search &s = P.s;
@@ -629,6 +661,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
             a.in_len = (int32_t)st.in_len;
             a.n_tiles = st.tiles;
             a.vec_ok = si == 0 ? vec_ok : 1;
+            if (L.off_rec >= 0) a.rec = reinterpret_cast<spd::RecStep *>(P.ws + L.off_rec) + si;
             const int err = spd::launch_step(a, s.fam, st.lds_bytes, hip_stream);
             if (err) return hip_fail(err);
             if (const int e2 = mark()) return hip_fail(e2);
@@ -687,6 +720,12 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
     a.vec_ok = vec_ok;
     a.want_cand = want_cand;
     a.threshold = params->threshold;
+    if (gate) {
+        a.tile_flag = gate->flag;
+        a.tile_rows = gate->tile_rows;
+        a.tile_len = gate->tile_len;
+        a.n_col_tiles = gate->n_col_tiles;
+    }
     const int err = spd::launch_exhaustive(a, s.dense, hip_stream);
     if (err) return hip_fail(err);
     if (const int e2 = mark()) return hip_fail(e2);
@@ -727,12 +766,30 @@ spd::PeakArgs peak_args(const spd_params *params, const Prepared &P, int32_t n_d
         a.tile_slots[i] = L.tile_slots[i];
     }
     for (int i = 0; i <= I.n_levels; ++i) a.slab_base[i] = L.slab_base[i];
+    a.rec = nullptr;
+    if (L.off_rec >= 0) {
+        a.rec = reinterpret_cast<const spd::RecStep *>(P.ws + L.off_rec);
+        for (size_t si = 0; si < L.steps.size(); ++si)
+            for (int j = 0; j < L.steps[si].J; ++j) {
+                a.level_step[L.steps[si].k0 + j] = (int8_t)si;
+                a.level_j[L.steps[si].k0 + j] = (int8_t)j;
+            }
+    }
     return a;
 }
 
 int run_peaks(const spd_params *params, const Prepared &P, int32_t n_dm, int64_t t0,
-              spd_candidate *cand, int64_t cand_cap, int64_t *cand_count, void *hip_stream) {
-    const spd::PeakArgs a = peak_args(params, P, n_dm, t0, cand, cand_cap, cand_count);
+              spd_candidate *cand, int64_t cand_cap, int64_t *cand_count, void *hip_stream,
+              const Gate *gate = nullptr) {
+    spd::PeakArgs a = peak_args(params, P, n_dm, t0, cand, cand_cap, cand_count);
+    if (gate) {
+        a.tile_flag = gate->flag;
+        a.flag_mode = gate->mode;
+        a.tile_rows = gate->tile_rows;
+        a.tile_len = gate->tile_len;
+        a.n_col_tiles = gate->n_col_tiles;
+        a.base_count = gate->base;
+    }
     const int err = spd::launch_peaks(a, hip_stream);
     if (err) return hip_fail(err);
     return SPD_OK;
@@ -815,8 +872,9 @@ spd::BeamView beam_view(const spd_params *params, const BatchPlan &B, const spd_
     v.ld_out = st.ld_out;
     v.mean = bm.mean;
     v.sigma = bm.sigma;
-    v.Y = planes ? bm.snr : reinterpret_cast<float *>(ws + L.off_Y);
-    v.W = planes ? bm.width : reinterpret_cast<uint16_t *>(ws + L.off_W);
+    v.Y = planes ? bm.snr : nullptr;           // lossy only: candidates-only stores no planes
+    v.W = planes ? bm.width : nullptr;
+    v.rec = L.off_rec >= 0 ? reinterpret_cast<spd::RecStep *>(ws + L.off_rec) + si : nullptr;
     v.slab_cnt = reinterpret_cast<uint32_t *>(ws + L.off_cnt);
     v.slab_ent = reinterpret_cast<uint32_t *>(ws + L.off_ent);
     v.n_dm = bm.n_dm;
@@ -840,8 +898,8 @@ Prepared beam_prepared(const spd_params *params, const BatchPlan &B, const spd_b
     P.L = B.L[b];
     P.ws = ws_base + B.ws_off[b];
     const bool planes = params->flags & SPD_WRITE_PLANES;
-    P.Y = planes ? bm.snr : reinterpret_cast<float *>(P.ws + P.L.off_Y);
-    P.W = planes ? bm.width : reinterpret_cast<uint16_t *>(P.ws + P.L.off_W);
+    P.Y = planes ? bm.snr : nullptr;
+    P.W = planes ? bm.width : nullptr;
     return P;
 }
 
@@ -922,6 +980,72 @@ int spd_search(const spd_params *params, const float *x, int64_t ld, int32_t n_d
     st = run_filter(params, P, x, ld, n_dm, n_in, n_out, mean, sigma, hip_stream);
     if (st != SPD_OK || !want_cand) return st;
     return run_peaks(params, P, n_dm, t0, cand, cand_cap, cand_count, hip_stream);
+}
+
+// ---------------------------------------------------------------------------------------
+// Tile-gated search (spd.h: spd_gated_plan / spd_search_gated)
+// ---------------------------------------------------------------------------------------
+static int gated_check(const spd_params *lossy, const spd_params *exh, int32_t n_dm,
+                       int32_t n_in, int32_t n_out, int32_t tile_rows, int32_t tile_len,
+                       spd_plan_info *li, spd_plan_info *ei) {
+    if (!lossy || !exh || lossy->method == SPD_EXHAUSTIVE || exh->method != SPD_EXHAUSTIVE)
+        return SPD_EINVAL;
+    if (!(lossy->flags & SPD_WRITE_CANDIDATES) || !(exh->flags & SPD_WRITE_CANDIDATES))
+        return SPD_EINVAL;
+    if (tile_rows < 1 || tile_len < 1024 || tile_len % 1024) return SPD_EINVAL;
+    int st = spd_plan(lossy, n_dm, n_in, n_out, li);
+    if (st != SPD_OK) return st;
+    return spd_plan(exh, n_dm, n_in, n_out, ei);
+}
+
+int spd_gated_plan(const spd_params *lossy, const spd_params *exh, int32_t n_dm, int32_t n_in,
+                   int32_t n_out, int32_t tile_rows, int32_t tile_len, int64_t *workspace_bytes) {
+    if (!workspace_bytes) return SPD_EINVAL;
+    spd_plan_info li, ei;
+    const int st = gated_check(lossy, exh, n_dm, n_in, n_out, tile_rows, tile_len, &li, &ei);
+    if (st != SPD_OK) return st;
+    *workspace_bytes = round_up(li.workspace_bytes, 256) + round_up(ei.workspace_bytes, 256);
+    return SPD_OK;
+}
+
+int spd_search_gated(const spd_params *lossy, const spd_params *exh, const float *x, int64_t ld,
+                     int32_t n_dm, int32_t n_in, int32_t n_out, int64_t t0, const float *mean,
+                     const float *sigma, const uint8_t *tile_flag, int32_t tile_rows,
+                     int32_t tile_len, float *snr, uint16_t *width, float *exh_snr,
+                     uint16_t *exh_width, spd_candidate *cand, int64_t cand_cap,
+                     int64_t *cand_count, void *workspace, int64_t workspace_bytes,
+                     void *hip_stream) {
+    spd_plan_info li, ei;
+    int st = gated_check(lossy, exh, n_dm, n_in, n_out, tile_rows, tile_len, &li, &ei);
+    if (st != SPD_OK) return st;
+    if (!tile_flag || !x || !mean || !sigma || ld < n_in) return SPD_EINVAL;
+    if (cand_cap < 0 || (cand_cap > 0 && !cand) || !cand_count) return SPD_EINVAL;
+    if (t0 < 0 || (t0 & (((int64_t)1 << li.top_level) - 1))) return SPD_EALIGN;
+    const int64_t lw = round_up(li.workspace_bytes, 256);
+    if (!workspace || workspace_bytes < lw + round_up(ei.workspace_bytes, 256)) return SPD_EWORKSPACE;
+    Prepared PL, PE;
+    st = prepare(lossy, n_dm, n_in, n_out, snr, width, workspace, lw, &PL);
+    if (st != SPD_OK) return st;
+    st = prepare(exh, n_dm, n_in, n_out, exh_snr, exh_width, static_cast<char *>(workspace) + lw,
+                 workspace_bytes - lw, &PE);
+    if (st != SPD_OK) return st;
+    Gate g;
+    g.flag = tile_flag;
+    g.tile_rows = tile_rows;
+    g.tile_len = tile_len;
+    g.n_col_tiles = (int)ceil_div(n_out, tile_len);
+    // the lossy search everywhere; its candidates outside the flagged tiles come first
+    st = run_filter(lossy, PL, x, ld, n_dm, n_in, n_out, mean, sigma, hip_stream);
+    if (st != SPD_OK) return st;
+    g.mode = 1;
+    st = run_peaks(lossy, PL, n_dm, t0, cand, cand_cap, cand_count, hip_stream, &g);
+    if (st != SPD_OK) return st;
+    // the exhaustive set on the flagged tiles only; its candidates follow
+    st = run_filter(exh, PE, x, ld, n_dm, n_in, n_out, mean, sigma, hip_stream, nullptr, &g);
+    if (st != SPD_OK) return st;
+    g.mode = 2;
+    g.base = cand_count;
+    return run_peaks(exh, PE, n_dm, t0, cand, cand_cap, cand_count, hip_stream, &g);
 }
 
 int spd_batch_plan(const spd_params *params, int32_t n_beams, const spd_beam *beams,

@@ -48,6 +48,26 @@ struct StepLevel {
     int64_t slab_base;       // first pre-candidate slab of the level
 };
 
+// What the peak finder needs to form any slot of a cascade step again, bit for bit, when the
+// planes are not written (candidates only): the step's input series and the constants of its
+// levels.  Written into the workspace by the step's first work-group.
+struct RecLevel {
+    int32_t k, cshift, umax, ufull, base, slots;
+    uint64_t evalmask;
+    float rt[kMaxLevelWidths];        // the level's 1/sqrt(L) at [U-1]
+};
+
+struct RecStep {
+    const float *in;          // step input series (raw samples for the first step)
+    const float *cin;         // carried prefixes of the first level (BoxDIT, later steps), or null
+    const float *mean;
+    const float *sigma;
+    const float *rho;         // sigma-table ratios, or null
+    int64_t ld_in, ld_cin, ld_rho;
+    int32_t n_rho, in_len, n_in, normalise, carry, J;
+    RecLevel lv[kStepMaxLevels];
+};
+
 struct StepArgs {
     const float *in;          // step input series [n_dm][ld_in] (raw samples for the first step)
     const float *cin;         // carried prefixes of the first level [n_dm][ld_cin] (BoxDIT, k0 > 0)
@@ -76,6 +96,9 @@ struct StepArgs {
     int64_t ld_rho;
     int32_t n_rho;
     int32_t lds_sc;           // LDS offset (floats) of the per-row width scales (rho != null)
+    int32_t write_planes;     // store the planes (else the peak finder recomputes what it reads)
+    int32_t nth;              // threads per work-group (the planner's choice; single-beam launches)
+    RecStep *rec;             // where the first work-group records the step, or null
     StepLevel lv[kStepMaxLevels + 1];
     float rtab[kStepMaxLevels][kMaxLevelWidths];   // 1/sqrt(base + U 2^k) at [j][U-1]
 };
@@ -95,6 +118,7 @@ struct BeamView {
     uint32_t *slab_ent;
     int64_t ld_in, ld_cin, ld_out;
     int32_t n_dm, n_in, in_len, n_tiles, vec_ok, pad0;
+    RecStep *rec;               // the beam's record of this step (candidates only), or null
     int64_t plane_off[kStepMaxLevels];
     int64_t pitch[kStepMaxLevels];
     int64_t slab_base[kStepMaxLevels];
@@ -128,6 +152,10 @@ struct ExhArgs {
     int32_t vec_ok;
     int32_t want_cand;
     float threshold;
+    // tile-gated search: only work items in tiles whose flag is set are searched (the others
+    // record no pre-candidates and leave the planes untouched); null = every item
+    const uint8_t *tile_flag;   // [n_row_tiles][n_col_tiles]
+    int32_t tile_rows, tile_len, n_col_tiles;
 };
 
 struct ScaleArgs {
@@ -175,6 +203,17 @@ struct PeakArgs {
     int64_t slab_base[kMaxLevels + 1];
     int64_t level_pitch[kMaxLevels];
     int64_t level_off[kMaxLevels];
+    // planes not written (lossy, candidates only): slot values are formed again from the
+    // records of the cascade steps; level k is level level_j[k] of step level_step[k]
+    const RecStep *rec;
+    int8_t level_step[kMaxLevels];
+    int8_t level_j[kMaxLevels];
+    // tile gating: flag_mode 0 = every slot; 1 = candidates only in tiles whose flag is clear
+    // (the planes are complete); 2 = only in tiles whose flag is set, where the plane exists
+    // (neighbours in other tiles are absent).  Tile of (d, sample s): (d / tile_rows, s / tile_len).
+    const uint8_t *tile_flag;
+    int32_t flag_mode, tile_rows, tile_len, n_col_tiles;
+    const int64_t *base_count;  // candidates already in the list (written before it), or null
 };
 
 // Launchers (spd_kernels.hip).  Return hipError_t as int.

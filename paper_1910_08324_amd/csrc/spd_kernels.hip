@@ -220,6 +220,7 @@ struct ArgGeom {
     __device__ int64_t pitch(int j) const { return A.lv[j].pitch; }
     __device__ int64_t slab_base(int j) const { return A.lv[j].slab_base; }
     __device__ int slots(int j) const { return A.lv[j].slots; }
+    __device__ RecStep *rec() const { return A.rec; }
 };
 
 // The table is read-only during a launch and every lane of a work-group reads the same entry,
@@ -250,7 +251,46 @@ struct TabGeom {
     __device__ int64_t pitch(int j) const { return V->pitch[j]; }
     __device__ int64_t slab_base(int j) const { return V->slab_base[j]; }
     __device__ int slots(int j) const { return V->slots[j]; }
+    __device__ RecStep *rec() const { return V->rec; }
 };
+
+// The step's record for the peak finder (candidates only): pointers, sizes and level constants,
+// exactly those the tiles of this launch use.  Written by one work-group.
+template <int NTH, class G>
+__device__ __forceinline__ void write_rec(const StepArgs &A, const G &V, RecStep *R) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < A.J * kMaxLevelWidths; i += NTH) {
+        const int j = i / kMaxLevelWidths, u = i - j * kMaxLevelWidths;
+        R->lv[j].rt[u] = A.rtab[j][u];
+    }
+    if (tid < A.J) {
+        const StepLevel &L = A.lv[tid];
+        RecLevel &r = R->lv[tid];
+        r.k = L.k;
+        r.cshift = L.cshift;
+        r.umax = L.umax;
+        r.ufull = L.ufull;
+        r.base = L.base;
+        r.slots = V.slots(tid);
+        r.evalmask = L.evalmask;
+    }
+    if (tid == 0) {
+        R->in = V.in();
+        R->cin = V.cin();
+        R->mean = V.mean();
+        R->sigma = V.sigma();
+        R->rho = A.rho;
+        R->ld_in = V.ld_in();
+        R->ld_cin = V.ld_cin();
+        R->ld_rho = A.ld_rho;
+        R->n_rho = A.n_rho;
+        R->in_len = V.in_len();
+        R->n_in = V.n_in();
+        R->normalise = A.normalise;
+        R->carry = A.carry;
+        R->J = A.J;
+    }
+}
 
 // One tile (DM row d, tile `tile`) of a cascade launch.  A holds what every beam of the launch
 // shares (levels, width patterns, tile length); G the beam's buffers and sizes.
@@ -274,6 +314,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
     }
     const int64_t u0 = (int64_t)tile * T;
     if (tid < kStepMaxLevels) st_cnt[tid] = 0;
+    if (d == 0 && tile == 0 && V.rec()) write_rec<NTH>(A, V, V.rec());
 
     // ---- 1. window of the input series (normalised in the first step) and carried prefixes
     {
@@ -400,7 +441,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
                 int bw[kGroup];
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) bw[q] = bu[q] ? base + (bu[q] << k) : 0;
-                if (ma + kGroup <= V.slots(j)) {
+                if (!A.write_planes) {
+                    // candidates only: nothing stored; the peak finder forms what it reads again
+                } else if (ma + kGroup <= V.slots(j)) {
                     *reinterpret_cast<float4 *>(rowY + ma) = make_float4(best[0], best[1], best[2], best[3]);
                     *reinterpret_cast<uint2 *>(rowW + ma) =
                         make_uint2((uint32_t)bw[0] | ((uint32_t)bw[1] << 16),
@@ -598,6 +641,15 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
     const int g0 = (blockIdx.x - d * waves_per_row) * per;
     if (d >= A.n_dm) return;
     const int g_end = min(g0 + per, A.n_seg);
+    if (A.tile_flag) {
+        // tile-gated: a wave's items lie in one tile (tile_len is a multiple of 1024 samples)
+        const int64_t t = (int64_t)(d / A.tile_rows) * A.n_col_tiles + (g0 * kExhSlots) / A.tile_len;
+        if (!A.tile_flag[t]) {
+            if (A.want_cand && lane == 0)
+                for (int g = g0; g < g_end; ++g) A.slab_cnt[(int64_t)d * A.n_seg + g] = 0;
+            return;
+        }
+    }
     const int base = g0 * kExhSlots;
     const float *xr = A.x + (int64_t)d * A.ld;
     const float *srow = A.scale + (int64_t)d * A.scale_ld;     // this row's 1/sigma(L) factors
@@ -789,12 +841,122 @@ __global__ __launch_bounds__(64) void exh_kernel(const ExhArgs A) {
 // output in (level, dm, start) order without a global sort: per-wave survivor counts (each
 // slab's entries sorted in the wave), one scan, scatter.
 // ----------------------------------------------------------------------------------------
+// When only candidates are requested the lossy searches store no planes, and the peak finder
+// forms each slot value it reads again from the step's record: the units of the level as
+// pairwise sums of the step's input series (level by level, as the cascade forms them), the
+// BoxDIT carried prefix through the levels below, and the level's widths in increasing order
+// with the same FP32 operations as step_tile.  Value and width are therefore bitwise those the
+// planes would hold; the work is small because only slots near pre-candidates are formed.
+// ----------------------------------------------------------------------------------------
+__device__ __forceinline__ float rec_in(const RecStep &R, const float *inr, float mu, float inv,
+                                        int64_t r) {
+    if (r >= R.in_len) return 0.0f;                   // the tile pads past the data with zeros
+    return R.normalise ? (inr[r] - mu) * inv : inr[r];
+}
+
+// pairwise sum of the 2^J input units from a, in the cascade's order
+template <int J>
+__device__ __forceinline__ float rec_tree(const RecStep &R, const float *inr, float mu, float inv,
+                                          int64_t a) {
+    float v[1 << J];
+#pragma unroll
+    for (int i = 0; i < (1 << J); ++i) v[i] = rec_in(R, inr, mu, inv, a + i);
+#pragma unroll
+    for (int h = (1 << J); h > 1; h >>= 1) {
+#pragma unroll
+        for (int i = 0; i < h / 2; ++i) v[i] = v[2 * i] + v[2 * i + 1];
+    }
+    return v[0];
+}
+
+// unit n of level j of the step: y_j[n] = y_{j-1}[2n + cshift_j] + y_{j-1}[2n + cshift_j + 1]
+__device__ __noinline__ float rec_unit(const RecStep &R, const float *inr, float mu, float inv,
+                                       int j, int64_t n) {
+    int64_t a = n;
+    for (int i = j; i >= 1; --i) a = 2 * a + R.lv[i].cshift;
+    switch (j) {
+        case 0: return rec_in(R, inr, mu, inv, a);
+        case 1: return rec_tree<1>(R, inr, mu, inv, a);
+        case 2: return rec_tree<2>(R, inr, mu, inv, a);
+        case 3: return rec_tree<3>(R, inr, mu, inv, a);
+        case 4: return rec_tree<4>(R, inr, mu, inv, a);
+        default: return rec_tree<5>(R, inr, mu, inv, a);
+    }
+}
+
+// Y and W of slot m (absolute) of level j of the step, row d
+__device__ __noinline__ float rec_slot(const RecStep &R, int d, int j, int64_t m, int *w_out) {
+    const float *inr = R.in + (int64_t)d * R.ld_in;
+    float mu = 0.0f, inv = 1.0f;
+    if (R.normalise) {
+        mu = R.mean[d];
+        inv = 1.0f / R.sigma[d];
+    }
+    const RecLevel &L = R.lv[j];
+    // carried prefix (BoxDIT): from the previous step's hand-off, then through levels 0..j-1,
+    // each adding its ufull units at the slot that leads to m
+    float X = 0.0f;
+    if (R.carry && (j > 0 || R.cin != nullptr)) {
+        const int64_t p0 = m << j;
+        if (R.cin && p0 < R.lv[0].slots) X = R.cin[(int64_t)d * R.ld_cin + p0];
+        for (int i = 0; i < j; ++i) {
+            const int64_t p = m << (j - i);
+            const int uf = R.lv[i].ufull;
+            for (int u = 0; u < uf; ++u) X += rec_unit(R, inr, mu, inv, i, p + u);
+        }
+    }
+    const float *rr = R.rho ? R.rho + (int64_t)d * R.ld_rho : nullptr;
+    const int64_t room = (int64_t)R.n_in - (m << L.k);
+    float best = SPD_NEG_INF;
+    int bu = 0;
+    for (int u = 0; u < L.umax; ++u) {
+        X += rec_unit(R, inr, mu, inv, j, m + u);
+        if ((L.evalmask >> u) & 1ull) {
+            float r = L.rt[u];
+            if (rr) {
+                const double Lw = (double)L.base + ldexp((double)(u + 1), L.k);
+                r = (float)((double)L.rt[u] / rho_of_width(rr, R.n_rho, Lw));
+            }
+            float v = X * r;
+            if ((int64_t)L.base + ((int64_t)(u + 1) << L.k) > room) v = SPD_NEG_INF;
+            if (v > best) {
+                best = v;
+                bu = u + 1;
+            }
+        }
+    }
+    *w_out = bu ? L.base + (bu << L.k) : 0;
+    return best;
+}
+
 // The helpers take the arguments either from the launch (one beam) or from a per-beam table in
 // the constant address space (a batch); PA is the (qualified) PeakArgs type.
+// SNR (and width, if w) of slot m of level k in row d: from the planes, or formed again.
+template <class PA>
+__device__ __forceinline__ float slot_value(PA &A, int k, int d, int m, int *w) {
+    if (A.rec) {
+        int wl;
+        const float y = rec_slot(A.rec[A.level_step[k]], d, A.level_j[k], m, &wl);
+        if (w) *w = wl;
+        return y;
+    }
+    const int64_t i = A.level_off[k] + (int64_t)d * A.level_pitch[k] + m;
+    if (w) *w = A.W[i];
+    return A.Y[i];
+}
+
+// tile gating of the candidates (flag_mode): may slot m of level k in row d be a candidate, and
+// does its value exist (mode 2: only inside flagged tiles)?
+template <class PA>
+__device__ __forceinline__ bool slot_kept(PA &A, int k, int d, int m) {
+    if (A.flag_mode == 0) return true;
+    const int64_t s = (int64_t)m << A.level_shift[k];
+    const bool f = A.tile_flag[(int64_t)(d / A.tile_rows) * A.n_col_tiles + s / A.tile_len] != 0;
+    return A.flag_mode == 2 ? f : !f;
+}
+
 template <class PA>
 __device__ __forceinline__ bool peak_test(PA &A, int k, int d, int m, float y) {
-    const float *P = A.Y + A.level_off[k];
-    const int64_t pitch = A.level_pitch[k];
     const int slots = A.level_slots[k];
 #pragma unroll
     for (int a = -1; a <= 1; ++a) {
@@ -805,7 +967,8 @@ __device__ __forceinline__ bool peak_test(PA &A, int k, int d, int m, float y) {
             if (a == 0 && b == 0) continue;
             const int mn = m + b;
             if (mn < 0 || mn >= slots) continue;
-            const float yn = P[(int64_t)dn * pitch + mn];
+            if (A.flag_mode == 2 && !slot_kept(A, k, dn, mn)) continue;   // no value there
+            const float yn = slot_value(A, k, dn, mn, nullptr);
             const bool earlier = (a < 0) || (a == 0 && b < 0);
             if (earlier ? !(y > yn) : !(y >= yn)) return false;
         }
@@ -833,7 +996,7 @@ __device__ __forceinline__ SlabPos slab_decode(PA &A, int64_t s) {
 
 template <class PA>
 __device__ __forceinline__ float plane_at(PA &A, int k, int d, int m) {
-    return A.Y[A.level_off[k] + (int64_t)d * A.level_pitch[k] + m];
+    return slot_value(A, k, d, m, nullptr);
 }
 
 __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key, int lane) {
@@ -877,7 +1040,7 @@ __device__ __forceinline__ void peak_count_wave(PA &A, int w, int lane) {
                 if (lane < (int)cc) {
                     A.slab_ent[ss * A.slab_cap + lane] = key;
                     const int m = (int)key;
-                    ok = peak_test(A, p.k, p.d, m, plane_at(A, p.k, p.d, m));
+                    ok = slot_kept(A, p.k, p.d, m) && peak_test(A, p.k, p.d, m, plane_at(A, p.k, p.d, m));
                 }
                 msk = __ballot(ok);
                 nsurv = __popcll(msk);
@@ -885,7 +1048,7 @@ __device__ __forceinline__ void peak_count_wave(PA &A, int w, int lane) {
                 for (int mb = p.mlo; mb < p.mhi; mb += 64) {
                     const int m = mb + lane;
                     bool ok = false;
-                    if (m < p.mhi) {
+                    if (m < p.mhi && slot_kept(A, p.k, p.d, m)) {
                         const float y = plane_at(A, p.k, p.d, m);
                         ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
                     }
@@ -913,6 +1076,9 @@ template <class PA>
 __device__ __forceinline__ void peak_scan_block(PA &A, int64_t *part) {
     const int t = threadIdx.x;
     const int per = (A.n_waves + 1023) / 1024;
+    // candidates already written before this list (read before the first barrier: the last
+    // thread may overwrite the same count at the end)
+    const int64_t base = A.base_count ? *A.base_count : 0;
     int64_t loc = 0;
     for (int i = 0; i < per; ++i) {
         const int w = t * per + i;
@@ -926,7 +1092,7 @@ __device__ __forceinline__ void peak_scan_block(PA &A, int64_t *part) {
         part[t] += v;
         __syncthreads();
     }
-    int64_t run = part[t] - loc;                      // exclusive prefix
+    int64_t run = base + part[t] - loc;               // exclusive prefix
     for (int i = 0; i < per; ++i) {
         const int w = t * per + i;
         if (w < A.n_waves) {
@@ -934,7 +1100,7 @@ __device__ __forceinline__ void peak_scan_block(PA &A, int64_t *part) {
             run += A.wave_tot[w];
         }
     }
-    if (t == 1023) *A.cand_count = part[1023];
+    if (t == 1023) *A.cand_count = base + part[1023];
 }
 
 __global__ __launch_bounds__(1024) void peak_scan_kernel(const PeakArgs A) {
@@ -943,12 +1109,12 @@ __global__ __launch_bounds__(1024) void peak_scan_kernel(const PeakArgs A) {
 }
 
 template <class PA>
-__device__ __forceinline__ void put_cand(PA &A, int64_t idx, int k, int d, int m, float y) {
+__device__ __forceinline__ void put_cand(PA &A, int64_t idx, int k, int d, int m, float y, int w) {
     if (idx >= A.cand_cap) return;
     spd_candidate c;
     c.start = A.t0 + ((int64_t)m << A.level_shift[k]);
     c.dm = d;
-    c.width = A.W[A.level_off[k] + (int64_t)d * A.level_pitch[k] + m];
+    c.width = w;
     c.level = k;
     c.snr = y;
     A.cand[idx] = c;
@@ -975,8 +1141,9 @@ __device__ __forceinline__ void peak_scatter_wave(PA &A, int w, int lane) {
                 const uint64_t msk = A.mask[ss];
                 if (lane < (int)cc && ((msk >> lane) & 1ull)) {
                     const int m = (int)A.slab_ent[ss * A.slab_cap + lane];
-                    put_cand(A, off + __popcll(msk & lanes_below(lane)), p.k, p.d, m,
-                             plane_at(A, p.k, p.d, m));
+                    int w;
+                    const float y = slot_value(A, p.k, p.d, m, &w);
+                    put_cand(A, off + __popcll(msk & lanes_below(lane)), p.k, p.d, m, y, w);
                 }
             } else {
                 int64_t run = 0;
@@ -984,12 +1151,13 @@ __device__ __forceinline__ void peak_scatter_wave(PA &A, int w, int lane) {
                     const int m = mb + lane;
                     bool ok = false;
                     float y = 0.0f;
-                    if (m < p.mhi) {
-                        y = plane_at(A, p.k, p.d, m);
+                    int w = 0;
+                    if (m < p.mhi && slot_kept(A, p.k, p.d, m)) {
+                        y = slot_value(A, p.k, p.d, m, &w);
                         ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
                     }
                     const uint64_t b = __ballot(ok);
-                    if (ok) put_cand(A, off + run + __popcll(b & lanes_below(lane)), p.k, p.d, m, y);
+                    if (ok) put_cand(A, off + run + __popcll(b & lanes_below(lane)), p.k, p.d, m, y, w);
                     run += __popcll(b);
                 }
             }
@@ -1058,10 +1226,11 @@ int launch_evalmask(const MaskArgs &a, void *stream) {
     return (int)hipGetLastError();
 }
 
-// IG(1) tiles of at most kSmallTileMax units run on work-groups of kSmallStepThreads: its light
-// width sets leave the launch bound by the plane writes, which go faster from more, smaller
-// work-groups (3.77 ms against 3.91 ms at the best tile of either size on the 4096 x 262144 beam;
-// the denser sets are faster on 256 threads).  Results do not depend on the work-group size.
+// IG(1) tiles of at most kSmallTileMax units run on work-groups of kSmallStepThreads (the
+// planner sets StepArgs::nth): its light width sets leave the launch bound by the plane writes,
+// which go faster from more, smaller work-groups (3.77 ms against 3.91 ms at the best tile of
+// either size on the 4096 x 262144 beam; the denser sets are faster on 256 threads).  Results do
+// not depend on the work-group size.
 template <bool FIRST, int FAM, int NTH>
 static void launch_nth(const StepArgs &a, int lds_bytes, hipStream_t st) {
     const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_tiles));
@@ -1071,12 +1240,17 @@ static void launch_nth(const StepArgs &a, int lds_bytes, hipStream_t st) {
         hipLaunchKernelGGL((step_kernel<FIRST, FAM, false, NTH>), grid, dim3(NTH), lds_bytes, st, a);
 }
 
+// The work-group size is the planner's (StepArgs::nth): 128 threads only for IG(1).
 template <bool FIRST, int FAM>
 static int launch_one(const StepArgs &a, int lds_bytes, hipStream_t st) {
-    if (FAM == 1 && a.T <= kSmallTileMax)
-        launch_nth<FIRST, FAM, kSmallStepThreads>(a, lds_bytes, st);
-    else
+    if (a.nth == kSmallStepThreads) {
+        if (FAM != 1) return (int)hipErrorInvalidValue;
+        launch_nth<FIRST, 1, kSmallStepThreads>(a, lds_bytes, st);
+    } else if (a.nth == kStepThreads) {
         launch_nth<FIRST, FAM, kStepThreads>(a, lds_bytes, st);
+    } else {
+        return (int)hipErrorInvalidValue;
+    }
     return (int)hipGetLastError();
 }
 

@@ -188,10 +188,28 @@ class StreamServer:
                                            ctypes.byref(wsb), ctypes.byref(tb)), "spd_batch_plan")
         return int(wsb.value), int(tb.value)
 
+    def window_ws_max(self, n_dm: int) -> int:
+        """The most workspace one window of n_dm rows can need, alone in a batch or beside the
+        longest window (whose tile lengths the batch then takes).  The workspace is not monotone
+        in the window length (tile counts, hence pre-candidate slabs, step with the tile length),
+        so every window length the server forms is planned."""
+        g, best = self.grain, 0
+        ref, _ = self._batch_plan([(n_dm, self.cap, self.cap)])
+        for n_out in range(g, self.cap + 1, g):
+            n_in = min(self.cap, n_out + self.l_end - 1)
+            if n_in < n_out:
+                break
+            alone, _ = self._batch_plan([(n_dm, n_in, n_out)])
+            pair, _ = self._batch_plan([(n_dm, self.cap, self.cap), (n_dm, n_in, n_out)])
+            best = max(best, alone, pair - ref)
+        return best
+
     def _make_slots(self, n_dm: int):
         # descriptor tables sized for a full batch of the largest windows; the workspace arena for
-        # the budget, or for every slot holding such a batch if that is less
-        full, tb = self._batch_plan([(n_dm, self.cap, self.cap)] * self.max_reqs)
+        # the budget, or for every slot holding a full batch of the most demanding windows if
+        # that is less
+        _, tb = self._batch_plan([(n_dm, self.cap, self.cap)] * self.max_reqs)
+        full = self.max_reqs * (self.window_ws_max(n_dm) + 256)
         self.arena = _Arena(min(self.budget, self.n_slots * (full + 256)), self.device)
         for _ in range(self.n_slots):
             self.slots.append(_Slot(self.device, tb + 4096, self.max_reqs, self.cand_cap))

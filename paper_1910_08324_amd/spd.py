@@ -21,7 +21,7 @@ EXHAUSTIVE, BOXDIT, IGRID = 0, 1, 2
 WRITE_PLANES, WRITE_CANDIDATES = 1, 2
 MAX_LEVELS = 24
 MAX_LAUNCHES = 26
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 class Params(ctypes.Structure):
@@ -63,6 +63,8 @@ class PlanInfo(ctypes.Structure):
         ("launch_levels", ctypes.c_int32 * MAX_LAUNCHES),
         ("launch_in_units", ctypes.c_int64 * MAX_LAUNCHES),
         ("launch_out_units", ctypes.c_int64 * MAX_LAUNCHES),
+        ("launch_threads", ctypes.c_int32 * MAX_LAUNCHES),
+        ("launch_tile", ctypes.c_int32 * MAX_LAUNCHES),
     ]
 
 
@@ -100,6 +102,13 @@ def load():
         lib.spd_peaks.argtypes = [ctypes.POINTER(Params), i32, i32, i32, i64, P, P, P, i64, P, P,
                                   i64, P]
         lib.spd_peaks.restype = ctypes.c_int
+        lib.spd_gated_plan.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Params), i32, i32,
+                                       i32, i32, i32, ctypes.POINTER(i64)]
+        lib.spd_gated_plan.restype = ctypes.c_int
+        lib.spd_search_gated.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(Params), P, i64,
+                                         i32, i32, i32, i64, P, P, P, i32, i32, P, P, P, P, P,
+                                         i64, P, P, i64, P]
+        lib.spd_search_gated.restype = ctypes.c_int
         lib.spd_error_string.argtypes = [ctypes.c_int]
         lib.spd_error_string.restype = ctypes.c_char_p
         lib.spd_abi_version.argtypes = []
@@ -300,6 +309,68 @@ def search(x, mean, sigma, cfg: Config, n_in: Optional[int] = None, n_out: Optio
                         ptr(out.count) if cfg.candidates else None, ptr(workspace),
                         workspace.numel(), ctypes.c_void_p(stream))
     _check(st, "spd_search")
+    out._workspace = workspace
+    return out
+
+
+@dataclasses.dataclass
+class GatedResult:
+    lossy: Result                        # the lossy search's planes (if requested)
+    exh: Result                          # the exhaustive plane, written in flagged tiles only
+    cand: "torch.Tensor"                 # raw candidate bytes (device)
+    count: "torch.Tensor"                # int64[1] total candidates (device)
+
+    def candidates_host(self) -> np.ndarray:
+        total = int(self.count.cpu().item())
+        n = min(total, self.cand.numel() // CANDIDATE_DTYPE.itemsize)
+        return self.cand[: n * CANDIDATE_DTYPE.itemsize].cpu().numpy().view(CANDIDATE_DTYPE)
+
+
+def search_gated(x, mean, sigma, lossy: Config, exh: Config, tile_flag, tile_rows: int,
+                 tile_len: int, n_in: Optional[int] = None, n_out: Optional[int] = None,
+                 t0: int = 0, cand_cap: int = 1 << 20, workspace=None, out=None,
+                 stream=None) -> GatedResult:
+    """spd_search_gated: `lossy` everywhere, the exhaustive config `exh` on the tiles whose
+    flag (uint8 device tensor [ceil(n_dm / tile_rows)][ceil(n_out / tile_len)]) is set."""
+    import torch
+    n_dm, n = x.shape
+    n_in = n if n_in is None else int(n_in)
+    n_out = n_in if n_out is None else int(n_out)
+    if tile_flag.dtype != torch.uint8 or not tile_flag.is_contiguous() or tile_flag.numel() != \
+            (-(-n_dm // tile_rows)) * (-(-n_out // tile_len)):
+        raise ValueError("tile_flag must be a contiguous uint8 [row tiles][column tiles] tensor")
+    pl, kl = lossy.params()
+    pe, ke = exh.params()
+    lib = load()
+    li, ei = PlanInfo(), PlanInfo()
+    _check(lib.spd_plan(ctypes.byref(pl), n_dm, n_in, n_out, ctypes.byref(li)), "spd_plan")
+    _check(lib.spd_plan(ctypes.byref(pe), n_dm, n_in, n_out, ctypes.byref(ei)), "spd_plan")
+    wsb = ctypes.c_int64()
+    _check(lib.spd_gated_plan(ctypes.byref(pl), ctypes.byref(pe), n_dm, n_in, n_out, tile_rows,
+                              tile_len, ctypes.byref(wsb)), "spd_gated_plan")
+    dev = x.device
+    if out is None:
+        mk = lambda info, cfg: Result(
+            info, torch.empty(int(info.plane_elems), dtype=torch.float32, device=dev) if cfg.planes else None,
+            torch.empty(int(info.plane_elems), dtype=torch.int16, device=dev) if cfg.planes else None,
+            None, None, n_dm)
+        out = GatedResult(mk(li, lossy), mk(ei, exh),
+                          torch.empty(max(1, cand_cap) * CANDIDATE_DTYPE.itemsize,
+                                      dtype=torch.uint8, device=dev),
+                          torch.zeros(1, dtype=torch.int64, device=dev))
+    if workspace is None:
+        workspace = torch.empty(max(256, int(wsb.value)), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    cap = out.cand.numel() // CANDIDATE_DTYPE.itemsize
+    st = lib.spd_search_gated(ctypes.byref(pl), ctypes.byref(pe), ptr(x), x.stride(0), n_dm, n_in,
+                              n_out, int(t0), ptr(mean), ptr(sigma), ptr(tile_flag), int(tile_rows),
+                              int(tile_len), ptr(out.lossy.snr), ptr(out.lossy.width),
+                              ptr(out.exh.snr), ptr(out.exh.width), ptr(out.cand), cap,
+                              ptr(out.count), ptr(workspace), workspace.numel(),
+                              ctypes.c_void_p(stream))
+    _check(st, "spd_search_gated")
     out._workspace = workspace
     return out
 

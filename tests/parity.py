@@ -84,11 +84,14 @@ def check_planes(gpu_planes, ref_planes, x, mu, sg, n_in, what="", width_sigma=N
     return stats
 
 
-def check_candidates(cands, ref_planes, threshold, t0=0, rows=None, what="", start_end=None):
+def check_candidates(cands, ref_planes, threshold, t0=0, rows=None, what="", start_end=None,
+                     keep=None):
     """cands: structured array from the GPU.  rows: restrict the check to these DM rows (the
     reference planes must then hold rows rows-1..rows+1, indexed by `row_index`).
     start_end: the GPU list covers only starts below it (the reference planes still cover the
-    whole series, so the neighbours of the last covered slots are known)."""
+    whole series, so the neighbours of the last covered slots are known).
+    keep: per level, a boolean mask of the slots the GPU list may hold (the others are neither
+    required nor allowed; their values still act as neighbours)."""
     got = {}
     for c in cands:
         key = (int(c["level"]), int(c["dm"]), int(c["start"]))
@@ -101,6 +104,8 @@ def check_candidates(cands, ref_planes, threshold, t0=0, rows=None, what="", sta
     for lev, r in enumerate(ref_planes):
         k = r["k"]
         rob, pos = peaks.margin_masks(r["Y"], threshold, TOL)
+        if keep is not None:
+            rob, pos = rob & keep[lev], pos & keep[lev]
         d_idx, m_idx = np.nonzero(rob)
         for d, m in zip(d_idx.tolist(), m_idx.tolist()):
             key = (lev, d, t0 + (m << k))

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(lib):
                           "spd_prop_adam", "spd_tile_max", "spd_prop_labels"}
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.spd_abi_version() == spd.ABI_VERSION == 4
+    assert lib.spd_abi_version() == spd.ABI_VERSION == 5
 
 
 CASES = [("exh", 1), ("exh", 256), ("exh", 8192), ("dit", 8192)] + \
@@ -316,3 +316,37 @@ def test_msd_argument_checks(lib):
     assert args(P((1 << 20) + 8), need) == spd.SPD_EALIGN
     assert args(P(1 << 20), need, mean=None) == spd.SPD_EINVAL
     assert args(P(1 << 20), need, tau=0.0) == spd.SPD_EINVAL
+
+
+def test_candidates_only_workspace_is_small(lib):
+    """Lossy candidates-only searches keep no planes in the workspace (only the hand-off series,
+    the pre-candidate slabs and the step records); the exhaustive search still does."""
+    for m in ("ig1", "ig2", "ig3", "bd8", "bd16", "bd32", "dit"):
+        full = spd.plan(spd.Config(m, 8192), 4096, 262144)
+        info = spd.plan(spd.Config(m, 8192, planes=False), 4096, 262144)
+        assert info.workspace_bytes <= full.workspace_bytes + 65536, m
+        assert info.workspace_bytes < 0.1 * full.plane_elems * 6, m
+    ex = spd.plan(spd.Config("exh", 256, planes=False), 64, 65536)
+    assert ex.workspace_bytes >= ex.plane_elems * 6
+
+
+def test_gated_plan_host_checks(lib):
+    """spd_gated_plan: lossy + exhaustive parameter pair, candidates required, tile shape."""
+    import ctypes
+    pl, kl = spd.Config("ig1", 512).params()
+    pe, ke = spd.Config("exh", 512).params()
+    b = ctypes.c_int64()
+    ok = lib.spd_gated_plan(ctypes.byref(pl), ctypes.byref(pe), 40, 9000, 9000, 16, 4096,
+                            ctypes.byref(b))
+    assert ok == spd.SPD_OK
+    li = spd.plan(spd.Config("ig1", 512), 40, 9000)
+    ei = spd.plan(spd.Config("exh", 512), 40, 9000)
+    assert b.value >= li.workspace_bytes + ei.workspace_bytes
+    bad = [(pe, pe, 16, 4096), (pl, pl, 16, 4096), (pl, pe, 0, 4096), (pl, pe, 16, 1000),
+           (pl, pe, 16, 512)]
+    for a, e, tr, tl in bad:
+        assert lib.spd_gated_plan(ctypes.byref(a), ctypes.byref(e), 40, 9000, 9000, tr, tl,
+                                  ctypes.byref(b)) == spd.SPD_EINVAL
+    pn, kn = spd.Config("exh", 512, candidates=False).params()
+    assert lib.spd_gated_plan(ctypes.byref(pl), ctypes.byref(pn), 40, 9000, 9000, 16, 4096,
+                              ctypes.byref(b)) == spd.SPD_EINVAL

@@ -17,23 +17,36 @@ def bench():
     return mod
 
 
-def info(segment, first_levels, n_out=262144):
-    slots = [0] * 24
-    slots[0] = n_out
-    return types.SimpleNamespace(segment=segment, launch_first_level=first_levels, plane_slots=slots)
+def info(segment, first_levels, threads):
+    return types.SimpleNamespace(segment=segment, launch_first_level=first_levels,
+                                 launch_threads=threads)
 
 
-def test_step_threads(bench):
-    # IG(1): 128 threads on tiles of at most 3072 units; later launches get tiles no longer than
-    # their first level's slots need
-    assert bench.step_threads("ig1", info(3072, [0, 5, 10]), 0) == 128
-    assert bench.step_threads("ig1", info(4096, [0, 4, 8]), 0) == 256
-    assert bench.step_threads("ig1", info(4096, [0, 4, 8]), 1) == 256      # 16384 slots: tile 4096
-    assert bench.step_threads("ig1", info(4096, [0, 4, 8]), 2) == 128      # 1024 slots: tile 1024
+def test_kernel_names_follow_planned_work_group_size(bench):
+    assert bench.launch_kernel_name("ig1", info(3072, [0, 5], [128, 128]), 0) == \
+        "spd::step_kernel<true, 1, false, 128>"
+    assert bench.launch_kernel_name("ig1", info(4096, [0, 4], [256, 256]), 1) == \
+        "spd::step_kernel<false, 1, false, 256>"
+    assert bench.launch_kernel_name("bd16", info(3072, [0, 5], [256, 256]), 1) == \
+        "spd::step_kernel<false, 5, false, 256>"
+
+
+def test_planner_reports_work_group_size():
+    """The planner's launch list carries each launch's work-group size and tile: IG(1) tiles of
+    at most 3072 units on 128 threads, later launches on tiles no longer than their slots need."""
+    from paper_1910_08324_amd import spd
+    i = spd.plan(spd.Config("ig1", 8192, segment=3072, step_levels=5), 4096, 262144)
+    assert [i.launch_threads[k] for k in range(i.n_launches)] == [128] * i.n_launches
+    assert i.launch_tile[0] == 3072
+    i = spd.plan(spd.Config("ig1", 8192, segment=4096, step_levels=4), 4096, 262144)
+    th = [i.launch_threads[k] for k in range(i.n_launches)]
+    tl = [i.launch_tile[k] for k in range(i.n_launches)]
+    assert th == [256, 256, 128] and tl == [4096, 4096, 1024]
     for m in ("ig2", "ig3", "bd8", "bd16", "bd32"):
-        assert bench.step_threads(m, info(2048, [0, 4]), 0) == 256
-    assert bench.launch_kernel_name("ig1", info(3072, [0, 5]), 0) == "spd::step_kernel<true, 1, false, 128>"
-    assert bench.launch_kernel_name("bd16", info(3072, [0, 5]), 1) == "spd::step_kernel<false, 5, false, 256>"
+        i = spd.plan(spd.Config(m, 8192, segment=2048), 4096, 262144)
+        assert all(i.launch_threads[k] == 256 for k in range(i.n_launches)), m
+    i = spd.plan(spd.Config("exh", 256), 64, 65536)
+    assert i.launch_threads[i.n_launches - 1] == 64 and i.launch_tile[i.n_launches - 1] == 0
 
 
 def test_read_traffic_by_shape(bench, tmp_path, monkeypatch):
