@@ -262,6 +262,27 @@ int spd_search_gated(const spd_params *lossy, const spd_params *exh, const float
                      int64_t *cand_count, void *workspace, int64_t workspace_bytes,
                      void *hip_stream);
 
+/*
+ * spd_search_noalloc: spd_search without a workspace argument, for callers that cannot allocate
+ *   device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ *   allocation).  The workspace is a fixed array inside the library, SPD_NOALLOC_SCRATCH_BYTES
+ *   per GPU, allocated with the library's code on each GPU it runs on and held until the
+ *   process ends.  Arguments, outputs and results are those of spd_search (bitwise: the same
+ *   kernels run); the call allocates and frees nothing.
+ *   Limit: searches whose spd_plan_info.workspace_bytes exceeds SPD_NOALLOC_SCRATCH_BYTES return
+ *   SPD_EWORKSPACE with nothing enqueued (use spd_search with a workspace of your own).
+ *   Sharing: every call on one GPU uses that GPU's one array, so calls that overlap in time on
+ *   one GPU (other streams, other threads) race on it; serialise them.  A call may follow the
+ *   previous one on the same stream at once: nothing in the array needs clearing.
+ *   The first call on a device resolves the array's device address (SPD_EHIP if that fails).
+ */
+#define SPD_NOALLOC_SCRATCH_BYTES (64 << 20)
+
+int spd_search_noalloc(const spd_params *params, const float *x, int64_t ld, int32_t n_dm,
+                       int32_t n_in, int32_t n_out, int64_t t0, const float *mean,
+                       const float *sigma, float *snr, uint16_t *width, spd_candidate *cand,
+                       int64_t cand_cap, int64_t *cand_count, void *hip_stream);
+
 /* Human-readable text for a status code (static storage; includes the last HIP error text for
  * SPD_EHIP on this thread). */
 const char *spd_error_string(int status);

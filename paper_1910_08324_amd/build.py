@@ -13,7 +13,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = [os.path.join(CSRC, "spd_kernels.hip"), os.path.join(CSRC, "spd_api.cpp"),
            os.path.join(CSRC, "prop_kernels.hip"), os.path.join(CSRC, "msd_kernels.hip"),
-           os.path.join(CSRC, "stream_kernels.hip")]
+           os.path.join(CSRC, "stream_kernels.hip"),
+           os.path.join(CSRC, "spd_noalloc.hip")]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -109,6 +109,9 @@ def load():
                                          i32, i32, i32, i64, P, P, P, i32, i32, P, P, P, P, P,
                                          i64, P, P, i64, P]
         lib.spd_search_gated.restype = ctypes.c_int
+        lib.spd_search_noalloc.argtypes = [ctypes.POINTER(Params), P, i64, i32, i32, i32, i64, P,
+                                           P, P, P, P, i64, P, P]
+        lib.spd_search_noalloc.restype = ctypes.c_int
         lib.spd_error_string.argtypes = [ctypes.c_int]
         lib.spd_error_string.restype = ctypes.c_char_p
         lib.spd_abi_version.argtypes = []
@@ -372,6 +375,48 @@ def search_gated(x, mean, sigma, lossy: Config, exh: Config, tile_flag, tile_row
                               ctypes.c_void_p(stream))
     _check(st, "spd_search_gated")
     out._workspace = workspace
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20     # SPD_NOALLOC_SCRATCH_BYTES of include/spd.h
+
+
+def search_noalloc(x, mean, sigma, cfg: Config, out: Result, n_in: Optional[int] = None,
+                   n_out: Optional[int] = None, t0: int = 0, stream=None) -> Result:
+    """spd_search_noalloc: the search with the library's fixed device workspace.  `out` holds
+    the caller's output buffers (e.g. a Result of spd.search on the same shape, or one made
+    by Result with planes/candidates sized by spd.plan); nothing is allocated here."""
+    import torch
+
+    if not (x.is_cuda and mean.is_cuda and sigma.is_cuda):
+        raise ValueError("x, mean and sigma must be device tensors")
+    if x.dtype != torch.float32 or x.dim() != 2 or x.stride(1) != 1:
+        raise ValueError("x must be 2-D float32 with unit stride along time")
+    n_dm, n = x.shape
+    n_in = n if n_in is None else int(n_in)
+    n_out = n_in if n_out is None else int(n_out)
+    p, keep = cfg.params()
+    info = PlanInfo()
+    lib = load()
+    _check(lib.spd_plan(ctypes.byref(p), n_dm, n_in, n_out, ctypes.byref(info)), "spd_plan")
+    if cfg.planes and (out.snr is None or out.snr.numel() < info.plane_elems):
+        raise ValueError("`out` planes are too small for this search")
+    out.info = info
+    out.n_dm = n_dm
+    cap = out.cand.numel() // CANDIDATE_DTYPE.itemsize if cfg.candidates else 0
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+
+    def ptr(t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    st = lib.spd_search_noalloc(ctypes.byref(p), ptr(x), x.stride(0), n_dm, n_in, n_out, int(t0),
+                                ptr(mean), ptr(sigma), ptr(out.snr) if cfg.planes else None,
+                                ptr(out.width) if cfg.planes else None,
+                                ptr(out.cand) if cfg.candidates else None, cap,
+                                ptr(out.count) if cfg.candidates else None,
+                                ctypes.c_void_p(stream))
+    _check(st, "spd_search_noalloc")
     return out
 
 
