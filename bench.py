@@ -187,6 +187,9 @@ def main():
     ap.add_argument("--step-levels", type=int, default=0,
                     help="levels per cascade launch with --segment (0: library's)")
     ap.add_argument("--profile-probe", action="store_true")
+    ap.add_argument("--outputs", choices=["planes+candidates", "candidates"],
+                    default="planes+candidates",
+                    help="outputs of the probe's search (--profile-probe)")
     ap.add_argument("--sweep", action="store_true",
                     help="the paper's performance shapes instead of the standard line: DM-count, "
                          "length and L_end sweeps for IG(1) and BD-16, and the small exhaustive "
@@ -273,6 +276,11 @@ def main():
     info = run.info
 
     if args.profile_probe:
+        if args.outputs == "candidates":
+            import dataclasses
+            cfg = dataclasses.replace(cfg, planes=False)
+            run = spd.Runner(x, mu, sg, cfg, cand_cap=1 << 22)
+            info = run.info
         for _ in range(4):
             run.search()
         torch.cuda.synchronize()
@@ -287,7 +295,7 @@ def main():
         torch.cuda.synchronize()
         strided_bytes = x[:, 64:].numel() * 4
         launches = [{"kernel": launch_kernel_name(args.method, info, i),
-                     "algorithmic_bytes": launch_bytes(info, i, w.n_dm)}
+                     "algorithmic_bytes": launch_bytes(info, i, w.n_dm, planes=cfg.planes)}
                     for i in range(info.n_launches)]
         print(json.dumps({"probe": "ok", "method": args.method, "search_launches": 4,
                           "segment": int(info.segment),

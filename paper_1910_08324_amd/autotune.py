@@ -60,17 +60,19 @@ class Tuner:
                 json.dump(self.cache, f, indent=1)
 
     def choose(self, method: str, l_end: int, n_in: int, device="cuda",
-               threshold: float = 5.0) -> Choice:
-        key = f"{method}/{l_end}/{bucket(n_in)}"
+               threshold: float = 5.0, planes: bool = True) -> Choice:
+        """Fastest launch shape for this method and length; `planes` False times the
+        candidates-only search (no plane stores), whose best shape can differ."""
+        key = f"{method}/{l_end}/{bucket(n_in)}" + ("" if planes else "/candidates")
         if key in self.cache:
             c = self.cache[key]
             return Choice(c["segment"], c["step_levels"], c["ms"], [tuple(m) for m in c["measured"]])
-        c = self._measure(method, l_end, bucket(n_in), device, threshold)
+        c = self._measure(method, l_end, bucket(n_in), device, threshold, planes)
         self.cache[key] = dataclasses.asdict(c)
         self._save()
         return c
 
-    def _measure(self, method, l_end, n, device, threshold) -> Choice:
+    def _measure(self, method, l_end, n, device, threshold, planes=True) -> Choice:
         import torch
         g = torch.Generator(device=device)
         g.manual_seed(self.seed)
@@ -83,7 +85,8 @@ class Tuner:
             shapes = [(T, J) for T in SEGMENTS for J in DEPTHS]
         measured = []
         for T, J in shapes:
-            cfg = spd.Config(method, l_end, threshold=threshold, segment=T, step_levels=J)
+            cfg = spd.Config(method, l_end, threshold=threshold, segment=T, step_levels=J,
+                             planes=planes)
             try:
                 r = spd.Runner(x, mu, sg, cfg, cand_cap=1 << 16)
             except spd.SpdError:
@@ -111,7 +114,8 @@ def tuned_groups(beams: Sequence, method: str, l_end: int, tuner: Tuner, thresho
     max_workspace_bytes.  Returns [(beam indices, config)]."""
     shapes: Dict[Tuple[int, int], List[int]] = {}
     for i, (x, _, _) in enumerate(beams):
-        c = tuner.choose(method, l_end, x.shape[1], device=x.device, threshold=threshold)
+        c = tuner.choose(method, l_end, x.shape[1], device=x.device, threshold=threshold,
+                         planes=planes)
         shapes.setdefault((c.segment, c.step_levels), []).append(i)
     out = []
     for (T, J), idx in shapes.items():
@@ -137,7 +141,8 @@ def tuned_batches(beams: Sequence, method: str, l_end: int, tuner: Tuner, thresh
     spd.Batch per group.  Returns [(beam indices, batch)]."""
     groups: Dict[Tuple[int, int], List[int]] = {}
     for i, (x, _, _) in enumerate(beams):
-        c = tuner.choose(method, l_end, x.shape[1], device=x.device, threshold=threshold)
+        c = tuner.choose(method, l_end, x.shape[1], device=x.device, threshold=threshold,
+                         planes=planes)
         groups.setdefault((c.segment, c.step_levels), []).append(i)
     out = []
     for (T, J), idx in groups.items():

@@ -209,6 +209,10 @@ struct Layout {
     int64_t off_scale = 0, off_mask = 0, off_cnt = 0, off_ent = 0, off_surv = 0, off_msk = 0;
     int64_t off_wtot = 0, off_woff = 0, off_Y = -1, off_W = -1;
     int64_t off_rec = -1;     // records of the cascade steps (lossy, candidates only)
+    int64_t off_amask = -1;   // above-threshold bits of every slot (lossy, candidates only)
+    int64_t amask_words = 0;
+    int64_t mask_off[kMaxLevels] = {0};
+    int mask_wps[kMaxLevels] = {0};
     int64_t scale_ld = 0;
 };
 
@@ -479,9 +483,23 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
     L->off_woff = take((int64_t)L->n_waves * 8);
     if (!(p->flags & SPD_WRITE_PLANES)) {
         if (lossy) {
-            // candidates only: no planes anywhere; the peak finder forms the few slot values it
-            // reads again from each step's record
+            // candidates only: no planes anywhere; the cascade leaves one bit per slot (above
+            // the threshold or not) and the peak finder forms the few slot values it needs
+            // again from each step's record
             L->off_rec = take((int64_t)L->steps.size() * (int64_t)sizeof(spd::RecStep));
+            int64_t words = 0;
+            for (int k = 0; k < nlev; ++k) {
+                L->mask_wps[k] = (int)ceil_div(L->tile_slots[k], 32);
+                L->mask_off[k] = words;
+                words += (int64_t)n_dm * L->tiles_per_row[k] * L->mask_wps[k];
+            }
+            L->off_amask = take(words * 4);
+            L->amask_words = words;
+            for (StepPlan &st : L->steps)
+                for (int j = 0; j < st.J; ++j) {
+                    st.lv[j].mask_off = L->mask_off[st.k0 + j];
+                    st.lv[j].mask_wps = L->mask_wps[st.k0 + j];
+                }
         } else {
             // the exhaustive search is bound by arithmetic: its planes go to the workspace
             L->off_Y = take(I.plane_elems * 4);
@@ -626,6 +644,13 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
                int32_t n_dm, int32_t n_in, int32_t n_out, const float *mean, const float *sigma,
                void *hip_stream, LaunchMarks *marks = nullptr, const Gate *gate = nullptr) {
     auto mark = [&]() { return marks ? marks->mark() : 0; };
+    if (P.L.off_amask >= 0) {
+        // candidates only: the cascade sets only the bits of slots above the threshold (this
+        // clearing is not one of the filter's listed launches)
+        const int err = spd::launch_fill_u32(reinterpret_cast<uint32_t *>(P.ws + P.L.off_amask),
+                                             P.L.amask_words, 0u, hip_stream);
+        if (err) return hip_fail(err);
+    }
     if (const int err = mark()) return hip_fail(err);
     const Search &s = P.s;
     const Layout &L = P.L;
@@ -638,6 +663,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
         const float *in = x;
         int64_t ld_in = ld;
         const float *cin = nullptr;
+
         for (size_t si = 0; si < L.steps.size(); ++si) {
             const StepPlan &st = L.steps[si];
             spd::StepArgs a;
@@ -662,6 +688,7 @@ int run_filter(const spd_params *params, const Prepared &P, const float *x, int6
             a.n_tiles = st.tiles;
             a.vec_ok = si == 0 ? vec_ok : 1;
             if (L.off_rec >= 0) a.rec = reinterpret_cast<spd::RecStep *>(P.ws + L.off_rec) + si;
+            if (L.off_amask >= 0) a.amask = reinterpret_cast<uint32_t *>(P.ws + L.off_amask);
             const int err = spd::launch_step(a, s.fam, st.lds_bytes, hip_stream);
             if (err) return hip_fail(err);
             if (const int e2 = mark()) return hip_fail(e2);
@@ -767,6 +794,13 @@ spd::PeakArgs peak_args(const spd_params *params, const Prepared &P, int32_t n_d
     }
     for (int i = 0; i <= I.n_levels; ++i) a.slab_base[i] = L.slab_base[i];
     a.rec = nullptr;
+    if (L.off_amask >= 0) {
+        a.amask = reinterpret_cast<const uint32_t *>(P.ws + L.off_amask);
+        for (int i = 0; i < I.n_levels; ++i) {
+            a.mask_off[i] = L.mask_off[i];
+            a.mask_wps[i] = L.mask_wps[i];
+        }
+    }
     if (L.off_rec >= 0) {
         a.rec = reinterpret_cast<const spd::RecStep *>(P.ws + L.off_rec);
         for (size_t si = 0; si < L.steps.size(); ++si)
@@ -875,6 +909,8 @@ spd::BeamView beam_view(const spd_params *params, const BatchPlan &B, const spd_
     v.Y = planes ? bm.snr : nullptr;           // lossy only: candidates-only stores no planes
     v.W = planes ? bm.width : nullptr;
     v.rec = L.off_rec >= 0 ? reinterpret_cast<spd::RecStep *>(ws + L.off_rec) + si : nullptr;
+    v.amask = L.off_amask >= 0 ? reinterpret_cast<uint32_t *>(ws + L.off_amask) : nullptr;
+    for (int j = 0; j < st.J; ++j) v.mask_off[j] = st.lv[j].mask_off;
     v.slab_cnt = reinterpret_cast<uint32_t *>(ws + L.off_cnt);
     v.slab_ent = reinterpret_cast<uint32_t *>(ws + L.off_ent);
     v.n_dm = bm.n_dm;
@@ -1110,6 +1146,14 @@ int spd_batch_search(const spd_params *params, int32_t n_beams, const spd_beam *
         if (st != SPD_OK) return st;
     }
     const char *t = static_cast<const char *>(table_dev);
+    for (int b = 0; b < n_beams; ++b) {
+        const Layout &L = B.L[b];
+        if (L.off_amask < 0) continue;
+        const int err = spd::launch_fill_u32(
+            reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + B.ws_off[b] + L.off_amask),
+            L.amask_words, 0u, hip_stream);
+        if (err) return hip_fail(err);
+    }
     for (int si = 0; si < B.n_steps; ++si) {
         const StepPlan &sp = B.L[0].steps[si];
         spd::StepBatchArgs a;

@@ -46,6 +46,9 @@ struct StepLevel {
     int64_t plane_off;       // element offset of the level's plane
     int64_t pitch;           // elements between rows of the plane
     int64_t slab_base;       // first pre-candidate slab of the level
+    int64_t mask_off;        // candidates only: first word of the level's above-threshold bits
+    int32_t mask_wps;        // words of above-threshold bits per (row, tile) slab
+    int32_t pad1;
 };
 
 // What the peak finder needs to form any slot of a cascade step again, bit for bit, when the
@@ -99,6 +102,7 @@ struct StepArgs {
     int32_t write_planes;     // store the planes (else the peak finder recomputes what it reads)
     int32_t nth;              // threads per work-group (the planner's choice; single-beam launches)
     RecStep *rec;             // where the first work-group records the step, or null
+    uint32_t *amask;          // above-threshold bits of the slots (candidates only), or null
     StepLevel lv[kStepMaxLevels + 1];
     float rtab[kStepMaxLevels][kMaxLevelWidths];   // 1/sqrt(base + U 2^k) at [j][U-1]
 };
@@ -119,6 +123,8 @@ struct BeamView {
     int64_t ld_in, ld_cin, ld_out;
     int32_t n_dm, n_in, in_len, n_tiles, vec_ok, pad0;
     RecStep *rec;               // the beam's record of this step (candidates only), or null
+    uint32_t *amask;            // the beam's above-threshold bits (candidates only), or null
+    int64_t mask_off[kStepMaxLevels];
     int64_t plane_off[kStepMaxLevels];
     int64_t pitch[kStepMaxLevels];
     int64_t slab_base[kStepMaxLevels];
@@ -208,6 +214,11 @@ struct PeakArgs {
     const RecStep *rec;
     int8_t level_step[kMaxLevels];
     int8_t level_j[kMaxLevels];
+    // bit (m - t tile_slots) of word mask_off[k] + (d tiles_per_row[k] + t) mask_wps[k] + .. / 32:
+    // slot m of level k in row d is above the threshold (candidates only)
+    const uint32_t *amask;
+    int64_t mask_off[kMaxLevels];
+    int32_t mask_wps[kMaxLevels];
     // tile gating: flag_mode 0 = every slot; 1 = candidates only in tiles whose flag is clear
     // (the planes are complete); 2 = only in tiles whose flag is set, where the plane exists
     // (neighbours in other tiles are absent).  Tile of (d, sample s): (d / tile_rows, s / tile_len).
@@ -226,6 +237,8 @@ int launch_step_batch(const StepBatchArgs &a, int fam, int lds_bytes, int grid, 
 uint64_t family_mask(int fam, int pattern);
 int launch_exhaustive(const ExhArgs &a, bool dense, void *stream);
 int launch_peaks(const PeakArgs &a, void *stream);
+// p[0 .. n) = v (a kernel, so that graph capture records no memset node)
+int launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, void *stream);
 
 // the peak finder over every beam of a batch: a device table of PeakArgs (16-byte aligned) and
 // the first global wave index of each beam (n_beams + 1 entries)

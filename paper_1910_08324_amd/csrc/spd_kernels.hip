@@ -12,6 +12,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include "spd_internal.h"
 
 namespace spd {
@@ -221,6 +223,8 @@ struct ArgGeom {
     __device__ int64_t slab_base(int j) const { return A.lv[j].slab_base; }
     __device__ int slots(int j) const { return A.lv[j].slots; }
     __device__ RecStep *rec() const { return A.rec; }
+    __device__ uint32_t *amask() const { return A.amask; }
+    __device__ int64_t mask_off(int j) const { return A.lv[j].mask_off; }
 };
 
 // The table is read-only during a launch and every lane of a work-group reads the same entry,
@@ -252,7 +256,18 @@ struct TabGeom {
     __device__ int64_t slab_base(int j) const { return V->slab_base[j]; }
     __device__ int slots(int j) const { return V->slots[j]; }
     __device__ RecStep *rec() const { return V->rec; }
+    __device__ uint32_t *amask() const { return V->amask; }
+    __device__ int64_t mask_off(int j) const { return V->mask_off[j]; }
 };
+
+// bits 0..7 of x to bits 0, 4, .., 28
+__device__ __forceinline__ uint32_t spread4(uint32_t x) {
+    x &= 0xffu;
+    x = (x | (x << 12)) & 0x000f000fu;
+    x = (x | (x << 6)) & 0x03030303u;
+    x = (x | (x << 3)) & 0x11111111u;
+    return x;
+}
 
 // The step's record for the peak finder (candidates only): pointers, sizes and level constants,
 // exactly those the tiles of this launch use.  Written by one work-group.
@@ -327,27 +342,47 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         const int N0 = A.lv[0].n_units;
         float *y0 = lds + A.lv[0].lds_y;
         const int64_t len = V.in_len();
-        for (int i = tid * 4; i < N0; i += NTH * 4) {
-            const int64_t r = u0 + i;
-            float4 v;
-            if (V.vec_ok() && r + 3 < len) {
-                v = *reinterpret_cast<const float4 *>(inr + r);
-                if (FIRST) {
-                    v.x = (v.x - mu) * inv;
-                    v.y = (v.y - mu) * inv;
-                    v.z = (v.z - mu) * inv;
-                    v.w = (v.w - mu) * inv;
-                }
-            } else {
-                float e[4];
+        // kLoadBatch float4 loads per thread are issued before any of them is used, so a tile's
+        // window costs about one memory round trip rather than one per float4
+        // (unconditional loads: lanes past the data read the row's last whole float4 instead,
+        // and use the element-wise path below)
+        constexpr int kLoadBatch = 8;
+        const bool vec = V.vec_ok() && len >= 4;
+        const int64_t rmax = vec ? ((len - 4) & ~(int64_t)3) : 0;
+        for (int i0 = tid * 4; i0 < N0; i0 += NTH * 4 * kLoadBatch) {
+            float4 v[kLoadBatch];
+            if (vec) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    e[q] = 0.0f;
-                    if (r + q < len) e[q] = FIRST ? (inr[r + q] - mu) * inv : inr[r + q];
+                for (int b = 0; b < kLoadBatch; ++b) {
+                    const int64_t r = u0 + i0 + b * NTH * 4;
+                    v[b] = *reinterpret_cast<const float4 *>(inr + (r < rmax ? r : rmax));
                 }
-                v = make_float4(e[0], e[1], e[2], e[3]);
             }
-            *reinterpret_cast<float4 *>(y0 + i) = v;
+#pragma unroll
+            for (int b = 0; b < kLoadBatch; ++b) {
+                const int i = i0 + b * NTH * 4;
+                if (i >= N0) continue;
+                const int64_t r = u0 + i;
+                float4 w;
+                if (vec && r + 3 < len) {
+                    w = v[b];
+                    if (FIRST) {
+                        w.x = (w.x - mu) * inv;
+                        w.y = (w.y - mu) * inv;
+                        w.z = (w.z - mu) * inv;
+                        w.w = (w.w - mu) * inv;
+                    }
+                } else {
+                    float e[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        e[q] = 0.0f;
+                        if (r + q < len) e[q] = FIRST ? (inr[r + q] - mu) * inv : inr[r + q];
+                    }
+                    w = make_float4(e[0], e[1], e[2], e[3]);
+                }
+                *reinterpret_cast<float4 *>(y0 + i) = w;
+            }
         }
         if (!FIRST && A.carry && V.cin()) {
             const float *cr = V.cin() + (int64_t)d * V.ld_cin();
@@ -460,6 +495,26 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
             if (A.want_cand) {
                 const float gmax = fmaxf(fmaxf(best[0], best[1]), fmaxf(best[2], best[3]));
                 if (__ballot(gmax > A.threshold)) {
+                    if (V.amask()) {
+                        // candidates only: one bit per slot, set where the SNR is above the
+                        // threshold (the bits start cleared).  Lane l of the wave holds slots
+                        // 4l .. 4l+3 from the wave's first group; lane w < 8 assembles the word
+                        // of slots 32w .. 32w+31.
+                        uint64_t bq[kGroup];
+#pragma unroll
+                        for (int q = 0; q < kGroup; ++q)
+                            bq[q] = __ballot(act && (ma + q < V.slots(j)) && best[q] > A.threshold);
+                        const int word = ((gb + 64 * (tid >> 6)) >> 3) + lane;
+                        if (lane < 8 && word < L.mask_wps) {
+                            uint32_t wbits = 0;
+#pragma unroll
+                            for (int q = 0; q < kGroup; ++q)
+                                wbits |= spread4((uint32_t)(bq[q] >> (8 * lane))) << q;
+                            if (wbits)
+                                V.amask()[V.mask_off(j) + ((int64_t)d * V.n_tiles() + tile) * L.mask_wps +
+                                          word] = wbits;
+                        }
+                    }
                     // time neighbours: inside the group, or the adjacent groups of the
                     // neighbouring lanes; unknown neighbours (wave edges) count as -inf
                     float left = __shfl_up(best[kGroup - 1], 1);
@@ -955,6 +1010,46 @@ __device__ __forceinline__ bool slot_kept(PA &A, int k, int d, int m) {
     return A.flag_mode == 2 ? f : !f;
 }
 
+// candidates only: is slot m of level k in row d above the threshold (its bit)?
+template <class PA>
+__device__ __forceinline__ bool slot_above(PA &A, int k, int d, int m) {
+    const int ts = A.tile_slots[k];
+    const int t = m / ts, lm = m - t * ts;
+    const uint32_t w = A.amask[A.mask_off[k] + ((int64_t)d * A.tiles_per_row[k] + t) * A.mask_wps[k] +
+                               (lm >> 5)];
+    return (w >> (lm & 31)) & 1u;
+}
+
+// The 3x3 test when the planes are not stored: a neighbour at or below the threshold cannot
+// block a slot above it, so only neighbours whose bit is set are formed again (and the slot
+// itself, once, if any is).
+template <class PA>
+__device__ __forceinline__ bool peak_test_rec(PA &A, int k, int d, int m) {
+    const int slots = A.level_slots[k];
+    bool have = false;
+    float y = 0.0f;
+#pragma unroll
+    for (int a = -1; a <= 1; ++a) {
+        const int dn = d + a;
+        if (dn < 0 || dn >= A.n_dm) continue;
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+            if (a == 0 && b == 0) continue;
+            const int mn = m + b;
+            if (mn < 0 || mn >= slots) continue;
+            if (!slot_above(A, k, dn, mn)) continue;
+            if (!have) {
+                y = slot_value(A, k, d, m, nullptr);
+                have = true;
+            }
+            const float yn = slot_value(A, k, dn, mn, nullptr);
+            const bool earlier = (a < 0) || (a == 0 && b < 0);
+            if (earlier ? !(y > yn) : !(y >= yn)) return false;
+        }
+    }
+    return true;
+}
+
 template <class PA>
 __device__ __forceinline__ bool peak_test(PA &A, int k, int d, int m, float y) {
     const int slots = A.level_slots[k];
@@ -1040,7 +1135,11 @@ __device__ __forceinline__ void peak_count_wave(PA &A, int w, int lane) {
                 if (lane < (int)cc) {
                     A.slab_ent[ss * A.slab_cap + lane] = key;
                     const int m = (int)key;
-                    ok = slot_kept(A, p.k, p.d, m) && peak_test(A, p.k, p.d, m, plane_at(A, p.k, p.d, m));
+                    if (A.amask)
+                        ok = slot_kept(A, p.k, p.d, m) && peak_test_rec(A, p.k, p.d, m);
+                    else
+                        ok = slot_kept(A, p.k, p.d, m) &&
+                             peak_test(A, p.k, p.d, m, plane_at(A, p.k, p.d, m));
                 }
                 msk = __ballot(ok);
                 nsurv = __popcll(msk);
@@ -1049,8 +1148,12 @@ __device__ __forceinline__ void peak_count_wave(PA &A, int w, int lane) {
                     const int m = mb + lane;
                     bool ok = false;
                     if (m < p.mhi && slot_kept(A, p.k, p.d, m)) {
-                        const float y = plane_at(A, p.k, p.d, m);
-                        ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
+                        if (A.amask) {
+                            ok = slot_above(A, p.k, p.d, m) && peak_test_rec(A, p.k, p.d, m);
+                        } else {
+                            const float y = plane_at(A, p.k, p.d, m);
+                            ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
+                        }
                     }
                     nsurv += __popcll(__ballot(ok));
                 }
@@ -1153,8 +1256,13 @@ __device__ __forceinline__ void peak_scatter_wave(PA &A, int w, int lane) {
                     float y = 0.0f;
                     int w = 0;
                     if (m < p.mhi && slot_kept(A, p.k, p.d, m)) {
-                        y = slot_value(A, p.k, p.d, m, &w);
-                        ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
+                        if (A.amask) {
+                            ok = slot_above(A, p.k, p.d, m) && peak_test_rec(A, p.k, p.d, m);
+                            if (ok) y = slot_value(A, p.k, p.d, m, &w);
+                        } else {
+                            y = slot_value(A, p.k, p.d, m, &w);
+                            ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
+                        }
                     }
                     const uint64_t b = __ballot(ok);
                     if (ok) put_cand(A, off + run + __popcll(b & lanes_below(lane)), p.k, p.d, m, y, w);
@@ -1337,6 +1445,20 @@ int launch_exhaustive(const ExhArgs &a, bool dense, void *stream) {
         else
             hipLaunchKernelGGL((exh_kernel<false, false, 64>), grid, dim3(64), 0, st, a);
     }
+    return (int)hipGetLastError();
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+int launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, void *stream) {
+    if (n <= 0) return 0;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       p, n, v);
     return (int)hipGetLastError();
 }
 

@@ -324,7 +324,9 @@ def test_candidates_only_workspace_is_small(lib):
     for m in ("ig1", "ig2", "ig3", "bd8", "bd16", "bd32", "dit"):
         full = spd.plan(spd.Config(m, 8192), 4096, 262144)
         info = spd.plan(spd.Config(m, 8192, planes=False), 4096, 262144)
-        assert info.workspace_bytes <= full.workspace_bytes + 65536, m
+        # plus one above-threshold bit per slot of every level (about 2 bits per sample)
+        bits = sum(int(full.plane_slots[k]) for k in range(full.n_levels)) * 4096
+        assert info.workspace_bytes <= full.workspace_bytes + 1.05 * bits / 8 + 65536, m
         assert info.workspace_bytes < 0.1 * full.plane_elems * 6, m
     ex = spd.plan(spd.Config("exh", 256, planes=False), 64, 65536)
     assert ex.workspace_bytes >= ex.plane_elems * 6
