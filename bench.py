@@ -198,6 +198,8 @@ def main():
                     help="tiles of 64 x 4096 to train the learned proposal on (0: skip)")
     ap.add_argument("--proposal-eval", type=int, default=8192, help="held-out evaluation tiles")
     ap.add_argument("--proposal-batch", type=int, default=256)
+    ap.add_argument("--proposal-beam", type=int, default=1,
+                    help="also gate the exhaustive search on the beam with the trained proposal")
     ap.add_argument("--no-msd", action="store_true", help="skip the noise-statistics section")
     ap.add_argument("--msd-probe", action="store_true",
                     help="only run the noise statistics of the beam a few times (for counter runs)")
@@ -205,7 +207,7 @@ def main():
     ap.add_argument("--msd-iter", type=int, default=10)
     ap.add_argument("--batch-beams", type=int, default=32,
                     help="beams of the batched multi-beam run (0: skip)")
-    ap.add_argument("--batch-dm-scale", type=int, default=8,
+    ap.add_argument("--batch-dm-scale", type=int, default=1,
                     help="divide the batched run's DM counts (512..4096) by this (1: full size)")
     ap.add_argument("--batch-ws-gb", type=float, default=120.0, help="workspace budget per fused group")
     ap.add_argument("--serve-blocks", type=int, default=24,
@@ -696,8 +698,11 @@ def msd_section(args, dev, x, w) -> dict:
 
 
 def batch_section(args, dev) -> dict:
-    """Many beams with uneven DM counts and lengths: tuned fused multi-beam launches against the
-    same beams searched one by one (candidates only; planes live in the workspace)."""
+    """Many beams with uneven DM counts and lengths, candidates only (no planes anywhere): one
+    fused launch per cascade step over all beams (library default launch shape), the autotuned
+    groups (beams of equal tuned shape fused), and the same beams one by one at those tuned
+    shapes.  Bytes against the 8 TB/s roof: the algorithmic ones of a candidates-only search
+    (every sample read once, plus the hand-offs between launches; no plane is written)."""
     import numpy as np
     import torch
     import synth
@@ -722,52 +727,73 @@ def batch_section(args, dev) -> dict:
     samples = sum(a * b for a, b in shapes)
     log(f"[bench] batch: {len(shapes)} beams, {samples * 4 / 2**30:.1f} GiB input, generated in "
         f"{time.time() - t:.1f} s")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def algo_bytes(cfg):
+        tot = 0
+        for x, _, _ in beams:
+            info = spd.plan(cfg, x.shape[0], x.shape[1])
+            tot += sum(launch_bytes(info, i, x.shape[0], planes=False) for i in range(info.n_launches))
+        return tot
+
+    # one fused launch per cascade step over every beam (the library's default launch shape)
+    cfg_all = spd.Config(args.method, 8192, threshold=5.0, planes=False)
+    b = spd.Batch(beams, cfg_all, cand_cap=1 << 20)
+    all_ms = timed(b.search)
+    all_cands = [r.candidates_host() for r in b.results]
+    all_steps = len([1 for i in range(b.results[0].info.n_launches)])
+    del b
+    torch.cuda.empty_cache()
+    # tuned groups (one fused launch per step and group)
     tuner = autotune.Tuner(rows=256, reps=2)
     t = time.time()
     groups = autotune.tuned_groups(beams, args.method, 8192, tuner, threshold=5.0,
                                    max_workspace_bytes=int(args.batch_ws_gb * 2**30))
     tune_s = time.time() - t
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fused_ms, desc = 0.0, []
+    fused_ms, desc, single_tuned_ms, same = 0.0, [], 0.0, True
     for idx, cfg in groups:
         b = spd.Batch([beams[i] for i in idx], cfg, cand_cap=1 << 20)
         b.grid = autotune.tune_batch_grid(b)
-        b.search()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(3):
-            b.search()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 3
+        ms = timed(b.search)
         fused_ms += ms
+        for j, i in enumerate(idx):
+            same = same and np.array_equal(b.results[j].candidates_host(), all_cands[i])
         desc.append({"beams": len(idx), "segment": cfg.segment, "step_levels": cfg.step_levels,
                      "grid": b.grid, "ms": round(ms, 3)})
         del b
         torch.cuda.empty_cache()
-    # the same beams one by one with the default launch shape
-    single_ms = 0.0
-    for x, mu, sg in beams:
-        r = spd.Runner(x, mu, sg, spd.Config(args.method, 8192, threshold=5.0, planes=False),
-                       cand_cap=1 << 20)
-        r.search()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(3):
-            r.search()
-        e1.record()
-        torch.cuda.synchronize()
-        single_ms += e0.elapsed_time(e1) / 3
-        del r
+        # the same beams one by one at the group's tuned shape
+        for i in idx:
+            x, mu, sg = beams[i]
+            r = spd.Runner(x, mu, sg, cfg, cand_cap=1 << 20)
+            single_tuned_ms += timed(r.search)
+            del r
     torch.cuda.empty_cache()
-    log(f"[bench] batch: fused {fused_ms:.2f} ms ({samples / (fused_ms * 1e-3):.3e} DM*samples/s) "
-        f"vs one by one {single_ms:.2f} ms; groups {desc}; tuning {tune_s:.1f} s")
+    byts = algo_bytes(cfg_all)
+    log(f"[bench] batch: one fused launch per step {all_ms:.2f} ms "
+        f"({samples / (all_ms * 1e-3):.3e} DM*samples/s, {byts / (all_ms * 1e-3) / 1e9:.0f} GB/s); "
+        f"tuned groups {fused_ms:.2f} ms; one by one at tuned shapes {single_tuned_ms:.2f} ms; "
+        f"groups {desc}; tuning {tune_s:.1f} s; candidates equal across groupings: {same}")
+    best = min(all_ms, fused_ms)
     return {"beams": len(shapes), "dm_scale": args.batch_dm_scale,
             "input_gib": round(samples * 4 / 2**30, 2), "samples": samples,
             "method": args.method, "l_end": 8192, "outputs": "candidates",
-            "fused_ms": round(fused_ms, 3), "one_by_one_ms": round(single_ms, 3),
-            "fused_dm_samples_per_s": samples / (fused_ms * 1e-3),
-            "one_by_one_dm_samples_per_s": samples / (single_ms * 1e-3),
+            "all_in_one_ms": round(all_ms, 3), "launches_per_search_all_in_one": all_steps,
+            "tuned_groups_ms": round(fused_ms, 3), "one_by_one_tuned_ms": round(single_tuned_ms, 3),
+            "dm_samples_per_s": samples / (best * 1e-3),
+            "algorithmic_bytes": byts,
+            "hbm_frac": round(byts / (best * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "candidates_equal_across_groupings": bool(same),
             "groups": desc, "tuning_seconds": round(tune_s, 1),
             "shapes": shapes}
 
@@ -922,22 +948,14 @@ def proposal_section(args, dev) -> dict:
     torch.cuda.synchronize()
     inf_ms = e0.elapsed_time(e1) / 10
     res = P.evaluate(net, args.proposal_eval, batch=B, seed=1, labeller=lab)
-    # modelled cost per tile of each path, from the measured per-batch stage times
-    t_lossy = t_exh = 0.0
-    e0.record()
-    lab.r_lossy.filter()
-    e1.record()
-    torch.cuda.synchronize()
-    t_lossy = e0.elapsed_time(e1)
-    e0.record()
-    lab.r_exh.filter()
-    e1.record()
-    torch.cuda.synchronize()
-    t_exh = e0.elapsed_time(e1)
-    cost_prop = t_lossy + inf_ms + res["flag_rate"] * t_exh
+    executed = gated_eval(args, dev, net, x, lab, B)
+    beam_gated = gated_beam(args, dev, net) if args.proposal_beam else None
     log(f"[bench] proposal: recall {res['recall']:.3f}, flag rate {res['flag_rate']:.3f}, mean loss "
         f"lossy {res['mean_loss_lossy'] * 100:.2f}% -> with proposal "
         f"{res['mean_loss_with_proposal'] * 100:.2f}%")
+    # forward pass FLOPs per tile: three 5-tap convolutions (8 -> 32, 32 -> 32, 32 -> 32 channels
+    # over 256 positions x 64 rows, 2 FLOP per multiply-add) and the 1 x 1 read-out
+    flop_tile = 64 * 256 * (2 * 32 * 5 * 8 + 2 * 2 * 32 * 5 * 32 + 2 * 32)
     return {"train_tiles": steps * B, "batch": B, "train_seconds": round(train_s, 2),
             "train_tiles_per_s": round(steps * B / train_s, 1),
             "loss_first": round(first_loss, 5), "loss_last": round(last_loss, 5),
@@ -947,12 +965,152 @@ def proposal_section(args, dev) -> dict:
                              "adam": round(per_batch[4], 3)},
             "inference_ms_per_batch": round(inf_ms, 4),
             "inference_tiles_per_s": round(B / (inf_ms * 1e-3), 1),
+            "inference_mfma_frac": round(flop_tile * B / (inf_ms * 1e-3) / 2.5e15, 4),
             "eval": res,
-            "ms_per_batch_lossy": round(t_lossy, 4), "ms_per_batch_exhaustive": round(t_exh, 4),
-            "ms_per_batch_lossy_plus_proposal": round(cost_prop, 4),
+            "executed": executed,
+            "beam": beam_gated,
             "workload": "tiles of 64 DM x 4096 samples, N(0,1) noise + 0-2 boxcar pulses "
                         "(width 1-64, SNR 6-30), labels: exhaustive 1..256 vs IG(1) L_end 256, "
                         "threshold 6, margin 1%"}
+
+
+def gated_eval(args, dev, net, x, lab, B) -> dict:
+    """The proposal-gated search executed on held-out blocks of B tiles (64 x 4096 each, stacked
+    by rows): features + forward + flag map + spd_search_gated, timed with HIP events against
+    the lossy search alone and the exhaustive search everywhere (all with planes + candidates).
+    Quality from what the gated search reported per tile, against the exhaustive maxima."""
+    import numpy as np
+    import torch
+    from paper_1910_08324_amd import proposal as P, spd
+
+    gs = P.GatedSearch(net, x, lab.mean, lab.sigma, lossy="ig1", l_end=256, threshold=6.0)
+    r_exh = spd.Runner(x, lab.mean, lab.sigma, spd.Config("exh", 256, threshold=6.0))
+    r_lossy = spd.Runner(x, lab.mean, lab.sigma, spd.Config("ig1", 256, threshold=6.0))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    n_b = max(1, args.proposal_eval // B)
+    t_gate = t_prop = t_lossy = t_exh = 0.0
+    E, Lm, Y, G, F = [], [], [], [], []
+    for i in range(n_b):
+        P.generate_tiles(1, (1 << 41) + i * B, B, out=x)
+        lab.run()                                      # reference maxima and labels
+        for rep in range(2):                           # second pass timed (warm)
+            ev[0].record()
+            gs.propose()
+            ev[1].record()
+            gs.search()
+            ev[2].record()
+        torch.cuda.synchronize()
+        t_prop += ev[0].elapsed_time(ev[1])
+        t_gate += ev[0].elapsed_time(ev[2])
+        for r, acc in ((r_lossy, "l"), (r_exh, "e")):
+            r.search()
+            ev[0].record()
+            r.search()
+            ev[3].record()
+            torch.cuda.synchronize()
+            if acc == "l":
+                t_lossy += ev[0].elapsed_time(ev[3])
+            else:
+                t_exh += ev[0].elapsed_time(ev[3])
+        E.append(lab.exh_max.cpu().numpy())
+        Lm.append(lab.lossy_max.cpu().numpy())
+        Y.append(lab.labels.cpu().numpy())
+        G.append(gs.tile_best().cpu().numpy().ravel())
+        F.append(gs.flag.cpu().numpy().ravel())
+    E, Lm, Y, G, F = (np.concatenate(a).astype(np.float64) for a in (E, Lm, Y, G, F))
+    pos, flag, sig = Y > 0.5, F > 0, E > 6.0
+    out = {"tiles": int(len(E)), "positives": int(pos.sum()), "flag_rate": float(flag.mean()),
+           "recall": float((flag & pos).sum() / max(1, pos.sum())),
+           "mean_loss_lossy": float(np.mean(1.0 - Lm[sig] / E[sig])),
+           "mean_loss_gated": float(np.mean(1.0 - G[sig] / E[sig])),
+           "max_loss_gated": float(np.max(1.0 - G[sig] / E[sig])),
+           "ms_per_block": {"propose": round(t_prop / n_b, 4), "gated_total": round(t_gate / n_b, 4),
+                            "lossy": round(t_lossy / n_b, 4), "exhaustive": round(t_exh / n_b, 4)},
+           "speedup_vs_exhaustive": round(t_exh / t_gate, 3),
+           "block": f"{B} tiles of 64 x 4096 (one column), IG(1) and exhaustive at L_end 256"}
+    log(f"[bench] gated (executed): {out['ms_per_block']}, flag rate {out['flag_rate']:.3f}, recall "
+        f"{out['recall']:.3f}, loss lossy {out['mean_loss_lossy'] * 100:.2f}% -> gated "
+        f"{out['mean_loss_gated'] * 100:.2f}% (max {out['max_loss_gated'] * 100:.2f}%)")
+    return out
+
+
+def gated_beam(args, dev, net) -> dict:
+    """The same trained proposal gating the exhaustive search (L_end 8192) on the 4096 x 262144
+    beam (64 x 64 tiles, 500 Gaussian pulses): measured time against the exhaustive search
+    everywhere, and per pulse tile the loss of the best reported SNR against the exhaustive one."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1910_08324_amd import proposal as P, spd
+
+    w = synth.ska_beam()
+    xb = torch.from_numpy(w.rows()).to(dev)
+    mu = torch.zeros(w.n_dm, device=dev)
+    sg = torch.ones(w.n_dm, device=dev)
+    gs = P.GatedSearch(net, xb, mu, sg, lossy="ig1", l_end=w.l_end, threshold=w.threshold)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    gs.run()
+    torch.cuda.synchronize()
+    e[0].record()
+    gs.propose()
+    e[1].record()
+    gs.search()
+    e[2].record()
+    torch.cuda.synchronize()
+    t_prop, t_all = e[0].elapsed_time(e[1]), e[0].elapsed_time(e[2])
+    flag = gs.flag.cpu().numpy()
+    # per pulse: the best SNR the gated search reports over boxcars starting in the pulse's
+    # window [start - L_end, start + width) of its row (lossy planes on unflagged tiles, the
+    # exhaustive plane on flagged tiles), against the exhaustive search's best there
+    fl_dev = gs.flag
+    def window_best(d, a, b):
+        tiles_c = fl_dev[d // 64]                                  # flags of the row's tiles
+        Ye, _ = gs.out.exh.level(0)
+        s = torch.arange(a, b, device=dev)
+        v = torch.where(tiles_c[s // 4096] != 0, Ye[d, a:b], torch.tensor(float("-inf"), device=dev))
+        best = v.max()
+        for i in range(gs.out.lossy.info.n_levels):
+            Yl, _ = gs.out.lossy.level(i)
+            k = int(gs.out.lossy.info.level_shift[i])
+            lo, hi = -(-a >> k), -(-b >> k)
+            if hi <= lo:
+                continue
+            m = torch.arange(lo, hi, device=dev)
+            v = torch.where(tiles_c[(m << k) // 4096] == 0, Yl[d, lo:hi],
+                            torch.tensor(float("-inf"), device=dev))
+            best = torch.maximum(best, v.max())
+        return best
+    wins = [(p.dm, max(0, p.start - w.l_end), min(w.n, p.start + p.width)) for p in w.pulses]
+    gbest = torch.stack([window_best(d, a, b) for d, a, b in wins]).cpu().numpy()
+    tiles = sorted({(p.dm // 64, min(63, (p.start + p.width // 2) // 4096)) for p in w.pulses})
+    rt, ct = np.array(tiles).T
+    del gs
+    torch.cuda.empty_cache()
+    r = spd.Runner(xb, mu, sg, spd.Config("exh", w.l_end, threshold=w.threshold, candidates=False))
+    e[0].record()
+    r.filter()
+    e[1].record()
+    torch.cuda.synchronize()
+    t_exh = e[0].elapsed_time(e[1])
+    Y, _ = r.result.level(0)
+    ebest = torch.stack([Y[d, a:b].max() for d, a, b in wins]).cpu().numpy()
+    del r, xb
+    torch.cuda.empty_cache()
+    sel = ebest > w.threshold
+    loss = 1.0 - gbest[sel] / ebest[sel]
+    out = {"tiles": 4096, "pulse_tiles": len(tiles), "flag_rate": float(flag.mean()),
+           "pulse_tiles_flagged": float(flag[rt, ct].mean()),
+           "ms_propose": round(t_prop, 3), "ms_gated_total": round(t_all, 3),
+           "ms_exhaustive": round(t_exh, 3), "speedup_vs_exhaustive": round(t_exh / t_all, 2),
+           "pulses_detected_by_exhaustive": int(sel.sum()),
+           "mean_loss_pulses": float(loss.mean()), "max_loss_pulses": float(loss.max()),
+           "note": "network trained on L_end-256 tiles (boxcar pulses of width 1-64); applied "
+                   "unchanged to the beam's Gaussian pulses at L_end 8192"}
+    log(f"[bench] gated on the beam: {t_all:.1f} ms (propose {t_prop:.2f}) vs exhaustive "
+        f"{t_exh:.1f} ms; flag rate {out['flag_rate']:.3f}, pulse tiles flagged "
+        f"{out['pulse_tiles_flagged']:.3f}, loss per pulse {out['mean_loss_pulses'] * 100:.2f}% "
+        f"(max {out['max_loss_pulses'] * 100:.2f}%)")
+    return out
 
 
 if __name__ == "__main__":

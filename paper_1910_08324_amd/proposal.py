@@ -39,9 +39,10 @@ def lib():
         L.spd_prop_adam.argtypes = [P, P, P, P, i32, ctypes.c_float, P]
         L.spd_tile_max.argtypes = [P, ctypes.POINTER(spd.PlanInfo), i32, i32, P, P]
         L.spd_prop_labels.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float, P, P]
+        L.spd_prop_flags.argtypes = [P, i32, i32, ctypes.c_float, P, P]
         for n in ("spd_tiles_generate", "spd_prop_features", "spd_prop_workspace",
                   "spd_prop_forward", "spd_prop_backward", "spd_prop_adam", "spd_tile_max",
-                  "spd_prop_labels"):
+                  "spd_prop_labels", "spd_prop_flags"):
             getattr(L, n).restype = ctypes.c_int
         _bound = True
     return L
@@ -134,6 +135,17 @@ def labels(exh_max, lossy_max, threshold: float, margin: float, out=None):
     spd._check(lib().spd_prop_labels(_p(exh_max), _p(lossy_max), exh_max.numel(),
                                      float(threshold), float(margin), _p(out),
                                      _stream(exh_max.device)), "spd_prop_labels")
+    return out
+
+
+def flags(logits, n_row_tiles: int, n_col_tiles: int, logit_threshold: float = 0.0, out=None):
+    """uint8 tile flag map [n_row_tiles][n_col_tiles] from logits in column order."""
+    import torch
+    if out is None:
+        out = torch.empty((n_row_tiles, n_col_tiles), dtype=torch.uint8, device=logits.device)
+    spd._check(lib().spd_prop_flags(_p(logits), int(n_row_tiles), int(n_col_tiles),
+                                    float(logit_threshold), _p(out), _stream(logits.device)),
+               "spd_prop_flags")
     return out
 
 
@@ -280,3 +292,65 @@ def summarize(E, Lm, Y, G, flag_logit: float = 0.0) -> dict:
             "detected_tiles": int(sig.sum()),
             "mean_loss_lossy": loss_lossy, "mean_loss_with_proposal": loss_prop,
             "mean_loss_missed_positives": missed_pos}
+
+
+class GatedSearch:
+    """The proposal-gated search of a block x [n_dm][n] (n_dm a multiple of 64, n of 4096):
+    DIT-level features of every 64 x 4096 tile, the network's logits, the tile flag map, then
+    spd_search_gated -- the lossy search everywhere and the exhaustive set on flagged tiles.
+    Every step is a library kernel; buffers are allocated once here."""
+
+    def __init__(self, net: "Network", x, mean, sigma, lossy: str = "ig1", l_end: int = 256,
+                 threshold: float = 6.0, logit_threshold: float = 0.0, cand_cap: int = 1 << 20,
+                 planes: bool = True):
+        import torch
+        n_dm, n = x.shape
+        if n_dm % TILE_ROWS or n % TILE_LEN:
+            raise ValueError("the block must hold whole 64 x 4096 tiles")
+        self.net, self.x, self.mean, self.sigma = net, x, mean, sigma
+        self.n_rt, self.n_ct = n_dm // TILE_ROWS, n // TILE_LEN
+        self.logit_threshold = float(logit_threshold)
+        dev = x.device
+        self.feat = torch.empty((self.n_ct * n_dm, ROW_POS, FEAT_CH), dtype=torch.int16, device=dev)
+        self.logits = torch.empty(self.n_ct * self.n_rt, dtype=torch.float32, device=dev)
+        self.flag = torch.zeros((self.n_rt, self.n_ct), dtype=torch.uint8, device=dev)
+        self.cfg_lossy = spd.Config(lossy, l_end, threshold=threshold, planes=planes)
+        self.cfg_exh = spd.Config("exh", l_end, threshold=threshold, planes=planes)
+        net._ensure(self.n_ct * self.n_rt)
+        self.out = spd.search_gated(x, mean, sigma, self.cfg_lossy, self.cfg_exh, self.flag,
+                                    TILE_ROWS, TILE_LEN, cand_cap=cand_cap)
+
+    def propose(self):
+        n_dm = self.x.shape[0]
+        for c in range(self.n_ct):
+            features(self.x[:, c * TILE_LEN:(c + 1) * TILE_LEN], self.mean, self.sigma,
+                     out=self.feat[c * n_dm:(c + 1) * n_dm])
+        self.net.forward(self.feat, self.n_ct * self.n_rt, self.logits)
+        flags(self.logits, self.n_rt, self.n_ct, self.logit_threshold, out=self.flag)
+
+    def search(self):
+        spd.search_gated(self.x, self.mean, self.sigma, self.cfg_lossy, self.cfg_exh, self.flag,
+                         TILE_ROWS, TILE_LEN, out=self.out, workspace=self.out._workspace)
+
+    def run(self):
+        self.propose()
+        self.search()
+        return self.out
+
+    def tile_best(self):
+        """Per tile [n_rt][n_ct] (device): the best SNR the gated search reports there -- the
+        exhaustive plane's maximum on flagged tiles, the lossy planes' elsewhere (planes mode)."""
+        import torch
+        n_dm = self.x.shape[0]
+        lo = torch.full((self.n_rt, self.n_ct), float("-inf"), device=self.x.device)
+        ex = torch.full_like(lo, float("-inf"))
+        for i in range(self.out.lossy.info.n_levels):
+            Y, _ = self.out.lossy.level(i)
+            k = int(self.out.lossy.info.level_shift[i])
+            per = TILE_LEN >> k
+            m = Y[:, : self.n_ct * per].reshape(self.n_rt, TILE_ROWS, self.n_ct, per)
+            lo = torch.maximum(lo, m.amax(dim=(1, 3)))
+        Y, _ = self.out.exh.level(0)
+        ex = Y[:, : self.n_ct * TILE_LEN].reshape(self.n_rt, TILE_ROWS, self.n_ct, TILE_LEN).amax(dim=(1, 3))
+        return torch.where(self.flag != 0, ex, lo)
+
