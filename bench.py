@@ -38,6 +38,10 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E peak
 # FP32 vector peak 157.3 TFLOP/s counts an FMA as 2 operations: 256 FLOP per clock per CU on
 # 256 CUs at 2.4 GHz, i.e. 128 single-operation lanes per clock per CU.
 VALU_PEAK_TOPS = 128 * 256 * 2.4e9 / 1e12
+# read the other way, 157.3 TFLOP/s counted as single operations (an FMA as 1)
+VALU_PEAK_TOPS_ALT = 157.3
+# FP64 vector: 78.6 TFLOP/s counting an FMA as 2, i.e. 64 lanes per clock per CU
+FP64_LANE_PEAK_TOPS = 64 * 256 * 2.4e9 / 1e12
 KERNEL_SRC = [os.path.join(ROOT, "paper_1910_08324_amd", "csrc", f)
               for f in ("spd_kernels.hip", "spd_internal.h", "spd_api.cpp")]
 PMC_FILE = os.path.join(ROOT, "profiles", "lossy_kernel_ska_beam_counters.txt")
@@ -135,6 +139,7 @@ def dominant_entry(method: str, cfg, run, w, reps: int, lms=None) -> dict:
     return {"kernel": launch_kernel_name(method, info, dom), "ms": round(lms[dom], 4),
             "launch_ms": [round(v, 4) for v in lms], "gbs": round(gbs, 1),
             "hbm_frac": round(hf, 4), "valu_tops": round(tops, 2), "valu_frac": round(vf, 4),
+            "valu_frac_vs_157": round(tops / VALU_PEAK_TOPS_ALT, 4),
             "bound": "hbm" if hf >= vf else "alu"}
 
 
@@ -469,6 +474,23 @@ def main():
                "sample": f"{done_rows} of {w.n_dm} DM rows x {w.n} samples, {args.method} planes "
                          f"(FP64 oracle, {spent:.1f} s)"}
         log(f"[bench] cpu oracle: {cpu['value']:.3e} DM*samples/s on {cpu['cores']} threads")
+        # the exhaustive oracle (every width 1..L_end) on whole rows of the same beam, as many as
+        # fit a few seconds, extrapolated per DM*sample (the work is linear in the rows)
+        lv_e = ow.method_levels("exh", w.l_end)
+        blk_e = min(w.n_dm, oplanes.threads())          # one row per oracle thread
+        rows_e, spent_e = 0, 0.0
+        while spent_e < args.cpu_seconds / 2 and rows_e + blk_e <= w.n_dm:
+            ta = time.perf_counter()
+            oplanes.planes(x_host[rows_e: rows_e + blk_e], np.zeros(blk_e, np.float32),
+                           np.ones(blk_e, np.float32), lv_e)
+            spent_e += time.perf_counter() - ta
+            rows_e += blk_e
+        cpu["exhaustive"] = {"value": rows_e * w.n / spent_e, "unit": "DM·samples/s",
+                             "rtf": round(w.n * T_SAMPLE / (spent_e / rows_e * w.n_dm), 5),
+                             "sample": f"{rows_e} DM rows x {w.n} samples, widths 1..{w.l_end} "
+                                       f"(FP64 oracle, {spent_e:.1f} s), extrapolated to "
+                                       f"{w.n_dm} rows"}
+        log(f"[bench] cpu exhaustive oracle: {cpu['exhaustive']['value']:.3e} DM*samples/s")
 
     hbm = hbm_section(dev, x)
     torch.cuda.empty_cache()
@@ -682,15 +704,23 @@ def msd_section(args, dev, x, w) -> dict:
     ms = e0.elapsed_time(e1) / reps
     nbytes = float(passes.sum().item()) * w.n * 4
     gbs = nbytes / (ms * 1e-3) / 1e9
+    vals_per_sample = sum(1.0 / (1 << k) for k in range(levels))
+    alg_ops = 5.0 * vals_per_sample * float(passes.sum().item()) * w.n
     res = {"levels": levels, "tau": args.msd_tau, "max_iter": args.msd_iter, "ms": round(ms, 4),
            "dm_samples_per_s": w.n_dm * w.n / (ms * 1e-3),
            "passes_mean": round(float(passes.mean().item()), 3),
            "passes_max": int(passes.max().item()),
-           # the sample reads against HBM; the kernel itself is bound by FP64 VALU issue (its SQ
-           # counters on this beam, profiles/msd_ska_beam_counters.txt)
-           "roofline": {"bound": "alu", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                        "basis": "sample reads x passes against HBM; FP64 VALU issue bounds it",
+           # bound by FP64 vector issue (SQ counters on this beam: the SIMDs issue a VALU
+           # instruction in 71% of cycles).  Algorithmic FP64 work: per value of every level
+           # the difference from the shift, the |d| <= limit test, the kept select, the sum and
+           # the sum of squares (5 operations); the levels hold about 2 values per sample.
+           # Peak: 256 CUs x 64 FP64 lanes x 2.4 GHz (78.6 TFLOP/s counting an FMA as 2).
+           "roofline": {"bound": "alu", "unit": "T FP64 op/s",
+                        "achieved": round(alg_ops / (ms * 1e-3) / 1e12, 3),
+                        "peak": FP64_LANE_PEAK_TOPS,
+                        "frac": round(alg_ops / (ms * 1e-3) / 1e12 / FP64_LANE_PEAK_TOPS, 4),
+                        "algorithmic_ops": alg_ops,
+                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                         "algorithmic_bytes": nbytes, "kernel": "spdm::msd_kernel"}}
     log(f"[bench] msd: {ms:.3f} ms for {w.n_dm} x {w.n}, {levels} levels, {res['passes_mean']} "
         f"passes per row on average: {gbs:.0f} GB/s of sample reads ({gbs / HBM_PEAK_GBS:.3f} of HBM)")
