@@ -7,11 +7,16 @@ separate stream keyed by (seed, PULSE_STREAM) and injected additively, one pulse
 Signal model (Section 2.1, "Idealized signal model"):
   * rectangular pulse of width S and amplitude A = C / sqrt(S), so that the boxcar of width S
     placed on the pulse recovers SNR C when mu = 0 and sigma = 1;
-  * Gaussian pulse: sampled normal profile over a support of S samples with its mean at S/2,
-    normalised like the rectangular one, i.e. the sum of all S samples equals C * sqrt(S)
-    (Section 4.3, "Other pulse shapes").  The support is S = max(1, round(2 * FWHM)), so the
-    FWHM is S / 2 (the reading of the paper's Gaussian width that reproduces its 20-sample
-    worked example).
+  * Gaussian pulse, worked-example form ("gauss"): sampled normal profile over a support of S
+    samples with its mean at S/2, normalised like the rectangular one, i.e. the sum of all S
+    samples equals C * sqrt(S) (Section 4.3, "Other pulse shapes").  The FWHM is S / 2 (the
+    reading of the paper's Gaussian width that reproduces its 20-sample worked example).
+  * Gaussian pulse of the benchmark beams ("gauss4"): FWHM given directly, sigma_g =
+    FWHM / (2 sqrt(2 ln 2)), sampled at the integers within +-4 sigma_g of the centre, scaled so
+    that the best boxcar of width <= l_max on the noise-free pulse has SNR exactly C (the
+    nominal SNR is then what an exhaustive search up to l_max recovers).  For a unimodal
+    symmetric profile the best window of L samples holds its L largest samples, so that SNR is
+    max over L of (sum of the L largest samples) / sqrt(L).
 
 This module holds none of the search arithmetic: no boxcar sums, no SNR evaluation.  It is
 shared by the CPU oracle and the GPU path only as a source of identical inputs.
@@ -37,8 +42,9 @@ class Pulse:
     start: int
     width: int
     snr: float
-    shape: str = "rect"  # "rect" or "gauss"
+    shape: str = "rect"  # "rect", "gauss" or "gauss4"
     fwhm: float = 0.0    # Gaussian only
+    l_max: int = 8192    # "gauss4": widest boxcar of the normalising search
 
     @property
     def centre(self) -> float:
@@ -84,7 +90,20 @@ def pulse_profile(p: Pulse) -> np.ndarray:
         if g.sum() <= 0.0:
             g[:] = 1.0
         return g * (p.snr * math.sqrt(S) / g.sum())
+    if p.shape == "gauss4":
+        sg = max(p.fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0))), 1e-3)
+        k = np.arange(S, dtype=np.float64)
+        g = np.exp(-0.5 * ((k - (S - 1) / 2.0) / sg) ** 2)
+        top = np.cumsum(np.sort(g)[::-1])[: max(1, min(S, int(p.l_max)))]
+        best = float(np.max(top / np.sqrt(np.arange(1, len(top) + 1, dtype=np.float64))))
+        return g * (p.snr / best)
     raise ValueError(f"unknown pulse shape {p.shape!r}")
+
+
+def gauss4_support(fwhm: float) -> int:
+    """Samples of a "gauss4" pulse: the integers within +-4 sigma_g of its centre (odd count)."""
+    sg = fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    return 2 * int(math.floor(4.0 * sg)) + 1
 
 
 def inject(x: np.ndarray, pulses: Sequence[Pulse], rows: Optional[Sequence[int]] = None) -> None:
@@ -119,8 +138,9 @@ def draw_rect_pulses(n_dm: int, n: int, count: int, seed: int, width_range=(1, 6
 
 
 def draw_gauss_pulses(n_dm: int, n: int, count: int, seed: int, fwhm_range=(1.0, 4096.0),
-                      snr_range=(5.0, 50.0), margin: int = 8192) -> List[Pulse]:
-    """`count` Gaussian pulses (in distinct rows when count <= n_dm); FWHM log-uniform, C ~ U[lo, hi)."""
+                      snr_range=(5.0, 50.0), margin: int = 8192, l_max: int = 8192) -> List[Pulse]:
+    """`count` "gauss4" pulses (in distinct rows when count <= n_dm); FWHM log-uniform,
+    C ~ U[lo, hi) the SNR of the best boxcar up to l_max on the noise-free pulse."""
     rng = _pulse_rng(seed)
     rows = rng.choice(n_dm, size=count, replace=count > n_dm)   # distinct rows while they last
     out = []
@@ -128,9 +148,10 @@ def draw_gauss_pulses(n_dm: int, n: int, count: int, seed: int, fwhm_range=(1.0,
     for d in sorted(int(r) for r in rows):
         fwhm = float(math.exp(rng.uniform(lo, hi)))
         C = float(rng.uniform(*snr_range))
-        S = max(1, int(round(2.0 * fwhm)))
+        S = gauss4_support(fwhm)
         start = int(rng.integers(margin, max(margin + 1, n - margin - S)))
-        out.append(Pulse(dm=d, start=start, width=S, snr=C, shape="gauss", fwhm=fwhm))
+        out.append(Pulse(dm=d, start=start, width=S, snr=C, shape="gauss4", fwhm=fwhm,
+                         l_max=l_max))
     return out
 
 

@@ -217,5 +217,43 @@ def test_training_gains_over_lossy_alone(P):
     assert hist[-1][1] < hist[0][1]
     pos_rate = ev["positives"] / ev["tiles"]
     assert ev["recall"] > 0.7 and ev["precision"] > 0.8
+    # at most 15% of all tiles flagged beyond the positive share (with precision > 0.8 above);
+    # the bound is relative to the mix because about 58% of these tiles are positive
     assert ev["flag_rate"] < pos_rate + 0.15
     assert ev["mean_loss_with_proposal"] < 0.5 * ev["mean_loss_lossy"]
+
+
+def test_gated_search_pipeline(P):
+    """proposal.GatedSearch on a block of 2 x 3 tiles: the flag map is the logits of the tiles
+    (features taken one column of tiles at a time) above the threshold, in row order, and the
+    gated search with that map is bitwise spd_search_gated's."""
+    from paper_1910_08324_amd import spd
+    say("[proposal] gated pipeline")
+    x = P.generate_tiles(5, 0, 6)                         # 6 tiles of 64 x 4096, stacked
+    # rearrange into a 128 x 12288 block: 2 row tiles x 3 column tiles
+    blk = torch.cat([torch.cat([x[(2 * c + r) * 64:(2 * c + r + 1) * 64] for c in range(3)], 1)
+                     for r in range(2)], 0).contiguous()
+    mu = torch.zeros(128, device="cuda")
+    sg = torch.ones(128, device="cuda")
+    net = P.Network(P.init_params(7), max_tiles=8)
+    gs = P.GatedSearch(net, blk, mu, sg, logit_threshold=0.0)
+    gs.propose()
+    torch.cuda.synchronize()
+    lg = gs.logits.cpu().numpy()
+    # logits in column order: tile (r, c) at c * 2 + r; each equals the network on that tile alone
+    for r in range(2):
+        for c in range(3):
+            f = P.features(blk[r * 64:(r + 1) * 64, c * 4096:(c + 1) * 4096].contiguous(), mu[:64], sg[:64])
+            one = net.forward(f, 1).cpu().numpy()[0]
+            assert abs(one - lg[c * 2 + r]) <= 1e-6 * max(1.0, abs(one))
+    thr = float(np.median(lg))
+    gs.logit_threshold = thr
+    gs.propose()
+    gs.search()
+    torch.cuda.synchronize()
+    want = np.ascontiguousarray((lg.reshape(3, 2).T > thr).astype(np.uint8))
+    assert np.array_equal(gs.flag.cpu().numpy(), want) and 0 < want.sum() < 6
+    ref = spd.search_gated(blk, mu, sg, gs.cfg_lossy, gs.cfg_exh, torch.from_numpy(want).cuda(),
+                           64, 4096)
+    torch.cuda.synchronize()
+    assert np.array_equal(gs.out.candidates_host(), ref.candidates_host())

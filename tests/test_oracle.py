@@ -381,3 +381,22 @@ def test_synth_rectangular_normalisation():
     assert np.allclose(prof, 3.0)
     g = synth.pulse_profile(synth.Pulse(0, 0, 40, 12.0, shape="gauss"))
     assert g.sum() == pytest.approx(12.0 * math.sqrt(40))
+
+
+@pytest.mark.parametrize("fwhm,snr", [(1.0, 10.0), (3.3, 20.0), (50.0, 7.0), (700.0, 30.0),
+                                      (4000.0, 12.0)])
+def test_gauss4_pulse_has_nominal_exhaustive_snr(fwhm, snr):
+    """The benchmark beam's Gaussian pulses (+-4 sigma_g support) are scaled so that the
+    noise-free exhaustive search up to L_end 8192 recovers the nominal SNR exactly (up to the
+    float32 rounding of the injected samples), centred on the pulse."""
+    S = synth.gauss4_support(fwhm)
+    p = synth.Pulse(0, 9000, S, snr, "gauss4", fwhm)
+    x = np.zeros((1, 9000 + S + 9000), np.float32)
+    synth.inject(x, [p])
+    R = planes.planes(x, np.zeros(1, np.float32), np.ones(1, np.float32),
+                      widths.method_levels("exh", 8192))
+    Y, W = R[0]["Y"].ravel(), R[0]["W"].ravel()
+    i = int(np.argmax(Y))
+    assert abs(Y[i] - snr) <= 1e-6 * snr
+    # the best boxcar is centred on the pulse (to within a sample)
+    assert abs((i + (W[i] - 1) / 2.0) - (9000 + (S - 1) / 2.0)) <= 1.0
