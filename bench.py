@@ -568,8 +568,12 @@ def candidates_only_section(args, cfg, x, mu, sg, w, C_planes) -> dict:
     import numpy as np
     import torch
 
-    from paper_1910_08324_amd import spd
+    from paper_1910_08324_amd import autotune, spd
     c2 = dataclasses.replace(cfg, planes=False)
+    if not args.no_tune and args.segment == 0:
+        # the candidates-only search has its own best launch shape (no plane stores)
+        ch = autotune.Tuner(rows=w.n_dm, reps=3).choose(args.method, w.l_end, w.n, planes=False)
+        c2 = dataclasses.replace(c2, segment=ch.segment, step_levels=ch.step_levels)
     run = spd.Runner(x, mu, sg, c2, cand_cap=1 << 22)
     for _ in range(args.warmup):
         run.search()
@@ -595,6 +599,7 @@ def candidates_only_section(args, cfg, x, mu, sg, w, C_planes) -> dict:
            "dm_samples_per_s": w.n_dm * w.n / (ms * 1e-3),
            "rtf": round(w.n * T_SAMPLE / (ms * 1e-3), 1),
            "algorithmic_bytes_per_dm_sample": round(in_bytes / (w.n_dm * w.n), 4),
+           "launch_shape": {"segment": c2.segment, "step_levels": c2.step_levels},
            "candidates_equal_planes_mode": same, "dominant": dom}
     log(f"[bench] {args.method} candidates only: {ms:.3f} ms/step (filter {filt:.3f}, peaks "
         f"{peak:.3f}), dominant {dom['kernel']} {dom['ms']} ms = {dom['hbm_frac']:.3f} of HBM; "

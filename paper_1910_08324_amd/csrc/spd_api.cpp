@@ -208,6 +208,8 @@ struct Layout {
     int tile_slots[kMaxLevels] = {0};
     int64_t off_scale = 0, off_mask = 0, off_cnt = 0, off_ent = 0, off_surv = 0, off_msk = 0;
     int64_t off_wtot = 0, off_woff = 0, off_Y = -1, off_W = -1;
+    int64_t cnt_off[kMaxLevels] = {0};
+    int cnt_stride[kMaxLevels] = {0};
     int64_t off_rec = -1;     // records of the cascade steps (lossy, candidates only)
     int64_t off_amask = -1;   // above-threshold bits of every slot (lossy, candidates only)
     int64_t amask_words = 0;
@@ -466,6 +468,23 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
     L->n_slabs = L->slab_base[nlev];
     for (StepPlan &st : L->steps)
         for (int j = 0; j < st.J; ++j) st.lv[j].slab_base = L->slab_base[st.k0 + j];
+    // pre-candidate counts: a cascade launch keeps the counts of its levels for one tile side by
+    // side; the exhaustive search has one level
+    {
+        int64_t cb = 0;
+        for (StepPlan &st : L->steps) {
+            for (int j = 0; j < st.J; ++j) {
+                st.lv[j].cnt_off = cb + j;
+                L->cnt_off[st.k0 + j] = cb + j;
+                L->cnt_stride[st.k0 + j] = st.J;
+            }
+            cb += (int64_t)n_dm * st.tiles * st.J;
+        }
+        if (L->steps.empty()) {
+            L->cnt_off[0] = 0;
+            L->cnt_stride[0] = 1;
+        }
+    }
     L->n_waves = (int)std::min<int64_t>(spd::kPeakWaves, L->n_slabs);
     L->slabs_per_wave = ceil_div(L->n_slabs, L->n_waves);
     L->n_waves = (int)ceil_div(L->n_slabs, L->slabs_per_wave);
@@ -483,13 +502,13 @@ int make_layout(const spd_params *p, const Search &s, int32_t n_dm, int32_t n_in
     L->off_woff = take((int64_t)L->n_waves * 8);
     if (!(p->flags & SPD_WRITE_PLANES)) {
         if (lossy) {
-            // candidates only: no planes anywhere; the cascade leaves one bit per slot (above
-            // the threshold or not) and the peak finder forms the few slot values it needs
-            // again from each step's record
+            // candidates only: no planes anywhere; the cascade leaves one bit per group of
+            // kGroup slots (any of them above the threshold or not) and the peak finder forms
+            // the few slot values it needs again from each step's record
             L->off_rec = take((int64_t)L->steps.size() * (int64_t)sizeof(spd::RecStep));
             int64_t words = 0;
             for (int k = 0; k < nlev; ++k) {
-                L->mask_wps[k] = (int)ceil_div(L->tile_slots[k], 32);
+                L->mask_wps[k] = (int)ceil_div(ceil_div(L->tile_slots[k], spd::kGroup), 32);
                 L->mask_off[k] = words;
                 words += (int64_t)n_dm * L->tiles_per_row[k] * L->mask_wps[k];
             }
@@ -793,6 +812,10 @@ spd::PeakArgs peak_args(const spd_params *params, const Prepared &P, int32_t n_d
         a.tile_slots[i] = L.tile_slots[i];
     }
     for (int i = 0; i <= I.n_levels; ++i) a.slab_base[i] = L.slab_base[i];
+    for (int i = 0; i < I.n_levels; ++i) {
+        a.cnt_off[i] = L.cnt_off[i];
+        a.cnt_stride[i] = L.cnt_stride[i];
+    }
     a.rec = nullptr;
     if (L.off_amask >= 0) {
         a.amask = reinterpret_cast<const uint32_t *>(P.ws + L.off_amask);
@@ -910,7 +933,10 @@ spd::BeamView beam_view(const spd_params *params, const BatchPlan &B, const spd_
     v.W = planes ? bm.width : nullptr;
     v.rec = L.off_rec >= 0 ? reinterpret_cast<spd::RecStep *>(ws + L.off_rec) + si : nullptr;
     v.amask = L.off_amask >= 0 ? reinterpret_cast<uint32_t *>(ws + L.off_amask) : nullptr;
-    for (int j = 0; j < st.J; ++j) v.mask_off[j] = st.lv[j].mask_off;
+    for (int j = 0; j < st.J; ++j) {
+        v.mask_off[j] = st.lv[j].mask_off;
+        v.cnt_off[j] = st.lv[j].cnt_off;
+    }
     v.slab_cnt = reinterpret_cast<uint32_t *>(ws + L.off_cnt);
     v.slab_ent = reinterpret_cast<uint32_t *>(ws + L.off_ent);
     v.n_dm = bm.n_dm;

@@ -46,8 +46,9 @@ struct StepLevel {
     int64_t plane_off;       // element offset of the level's plane
     int64_t pitch;           // elements between rows of the plane
     int64_t slab_base;       // first pre-candidate slab of the level
+    int64_t cnt_off;         // pre-candidate count of (row d, tile t) at cnt_off + (d n_tiles + t) J
     int64_t mask_off;        // candidates only: first word of the level's above-threshold bits
-    int32_t mask_wps;        // words of above-threshold bits per (row, tile) slab
+    int32_t mask_wps;        // words of above-threshold group bits per (row, tile) slab
     int32_t pad1;
 };
 
@@ -125,6 +126,7 @@ struct BeamView {
     RecStep *rec;               // the beam's record of this step (candidates only), or null
     uint32_t *amask;            // the beam's above-threshold bits (candidates only), or null
     int64_t mask_off[kStepMaxLevels];
+    int64_t cnt_off[kStepMaxLevels];
     int64_t plane_off[kStepMaxLevels];
     int64_t pitch[kStepMaxLevels];
     int64_t slab_base[kStepMaxLevels];
@@ -209,13 +211,18 @@ struct PeakArgs {
     int64_t slab_base[kMaxLevels + 1];
     int64_t level_pitch[kMaxLevels];
     int64_t level_off[kMaxLevels];
+    // the count of slab s = slab_base[k] + r (r = d tiles_per_row[k] + t) is slab_cnt[cnt_off[k] +
+    // r cnt_stride[k]]: a cascade launch writes the counts of its levels for one tile together
+    int64_t cnt_off[kMaxLevels];
+    int32_t cnt_stride[kMaxLevels];
     // planes not written (lossy, candidates only): slot values are formed again from the
     // records of the cascade steps; level k is level level_j[k] of step level_step[k]
     const RecStep *rec;
     int8_t level_step[kMaxLevels];
     int8_t level_j[kMaxLevels];
-    // bit (m - t tile_slots) of word mask_off[k] + (d tiles_per_row[k] + t) mask_wps[k] + .. / 32:
-    // slot m of level k in row d is above the threshold (candidates only)
+    // bit g % 32 of word mask_off[k] + (d tiles_per_row[k] + t) mask_wps[k] + g / 32, with
+    // g = (m - t tile_slots[k]) / kGroup: some slot of that group of level k in row d is above
+    // the threshold (candidates only)
     const uint32_t *amask;
     int64_t mask_off[kMaxLevels];
     int32_t mask_wps[kMaxLevels];

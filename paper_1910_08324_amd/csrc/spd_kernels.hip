@@ -225,6 +225,7 @@ struct ArgGeom {
     __device__ RecStep *rec() const { return A.rec; }
     __device__ uint32_t *amask() const { return A.amask; }
     __device__ int64_t mask_off(int j) const { return A.lv[j].mask_off; }
+    __device__ int64_t cnt_off(int j) const { return A.lv[j].cnt_off; }
 };
 
 // The table is read-only during a launch and every lane of a work-group reads the same entry,
@@ -258,16 +259,8 @@ struct TabGeom {
     __device__ RecStep *rec() const { return V->rec; }
     __device__ uint32_t *amask() const { return V->amask; }
     __device__ int64_t mask_off(int j) const { return V->mask_off[j]; }
+    __device__ int64_t cnt_off(int j) const { return V->cnt_off[j]; }
 };
-
-// bits 0..7 of x to bits 0, 4, .., 28
-__device__ __forceinline__ uint32_t spread4(uint32_t x) {
-    x &= 0xffu;
-    x = (x | (x << 12)) & 0x000f000fu;
-    x = (x | (x << 6)) & 0x03030303u;
-    x = (x | (x << 3)) & 0x11111111u;
-    return x;
-}
 
 // The step's record for the peak finder (candidates only): pointers, sizes and level constants,
 // exactly those the tiles of this launch use.  Written by one work-group.
@@ -348,7 +341,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         // and use the element-wise path below)
         constexpr int kLoadBatch = 8;
         const bool vec = V.vec_ok() && len >= 4;
-        const int64_t rmax = vec ? ((len - 4) & ~(int64_t)3) : 0;
+        // the last float4 a lane may read: inside the data and inside this tile's window (lanes
+        // past the window re-read it, served by the cache, instead of fetching the next tile's)
+        const int64_t rmax = vec ? min((len - 4) & ~(int64_t)3, u0 + ((N0 - 4) & ~3)) : 0;
         for (int i0 = tid * 4; i0 < N0; i0 += NTH * 4 * kLoadBatch) {
             float4 v[kLoadBatch];
             if (vec) {
@@ -496,23 +491,17 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
                 const float gmax = fmaxf(fmaxf(best[0], best[1]), fmaxf(best[2], best[3]));
                 if (__ballot(gmax > A.threshold)) {
                     if (V.amask()) {
-                        // candidates only: one bit per slot, set where the SNR is above the
-                        // threshold (the bits start cleared).  Lane l of the wave holds slots
-                        // 4l .. 4l+3 from the wave's first group; lane w < 8 assembles the word
-                        // of slots 32w .. 32w+31.
-                        uint64_t bq[kGroup];
-#pragma unroll
-                        for (int q = 0; q < kGroup; ++q)
-                            bq[q] = __ballot(act && (ma + q < V.slots(j)) && best[q] > A.threshold);
-                        const int word = ((gb + 64 * (tid >> 6)) >> 3) + lane;
-                        if (lane < 8 && word < L.mask_wps) {
-                            uint32_t wbits = 0;
-#pragma unroll
-                            for (int q = 0; q < kGroup; ++q)
-                                wbits |= spread4((uint32_t)(bq[q] >> (8 * lane))) << q;
-                            if (wbits)
-                                V.amask()[V.mask_off(j) + ((int64_t)d * V.n_tiles() + tile) * L.mask_wps +
-                                          word] = wbits;
+                        // candidates only: one bit per group of kGroup slots, set where any of
+                        // them is above the threshold (the bits start cleared): the wave's
+                        // ballot is its 64 groups, two words of the slab
+                        const uint64_t gbits = __ballot(act && gmax > A.threshold);
+                        const int word = (gb + 64 * (tid >> 6)) >> 5;
+                        if (lane == 0) {
+                            uint32_t *mw = V.amask() + V.mask_off(j) +
+                                           ((int64_t)d * V.n_tiles() + tile) * L.mask_wps + word;
+                            if ((uint32_t)gbits && word < L.mask_wps) mw[0] = (uint32_t)gbits;
+                            if ((uint32_t)(gbits >> 32) && word + 1 < L.mask_wps)
+                                mw[1] = (uint32_t)(gbits >> 32);
                         }
                     }
                     // time neighbours: inside the group, or the adjacent groups of the
@@ -577,7 +566,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
     }
     if (A.want_cand) {
         lds_barrier();
-        if (tid < A.J) V.slab_cnt()[V.slab_base(tid) + (int64_t)d * V.n_tiles() + tile] = st_cnt[tid];
+        // the tile's counts of all its levels side by side (one short write per work-group)
+        if (tid < A.J)
+            V.slab_cnt()[V.cnt_off(tid) + ((int64_t)d * V.n_tiles() + tile) * A.J] = st_cnt[tid];
     }
 }
 
@@ -1010,24 +1001,26 @@ __device__ __forceinline__ bool slot_kept(PA &A, int k, int d, int m) {
     return A.flag_mode == 2 ? f : !f;
 }
 
-// candidates only: is slot m of level k in row d above the threshold (its bit)?
+// candidates only: may slot m of level k in row d be above the threshold?  (The bit of its
+// group of kGroup slots: clear means every slot of the group is at or below the threshold.)
 template <class PA>
 __device__ __forceinline__ bool slot_above(PA &A, int k, int d, int m) {
     const int ts = A.tile_slots[k];
-    const int t = m / ts, lm = m - t * ts;
+    const int t = m / ts, g = (m - t * ts) / kGroup;
     const uint32_t w = A.amask[A.mask_off[k] + ((int64_t)d * A.tiles_per_row[k] + t) * A.mask_wps[k] +
-                               (lm >> 5)];
-    return (w >> (lm & 31)) & 1u;
+                               (g >> 5)];
+    return (w >> (g & 31)) & 1u;
 }
 
 // The 3x3 test when the planes are not stored: a neighbour at or below the threshold cannot
-// block a slot above it, so only neighbours whose bit is set are formed again (and the slot
-// itself, once, if any is).
+// block a slot above it, so only neighbours whose group bit is set are formed again (and the
+// slot itself, once, if any is; y_known: its value is already in y).
 template <class PA>
-__device__ __forceinline__ bool peak_test_rec(PA &A, int k, int d, int m) {
+__device__ __forceinline__ bool peak_test_rec(PA &A, int k, int d, int m, bool y_known = false,
+                                              float y_in = 0.0f) {
     const int slots = A.level_slots[k];
-    bool have = false;
-    float y = 0.0f;
+    bool have = y_known;
+    float y = y_in;
 #pragma unroll
     for (int a = -1; a <= 1; ++a) {
         const int dn = d + a;
@@ -1090,6 +1083,13 @@ __device__ __forceinline__ SlabPos slab_decode(PA &A, int64_t s) {
 }
 
 template <class PA>
+__device__ __forceinline__ int64_t slab_cnt_index(PA &A, int64_t s) {
+    int k = 0;
+    while (k + 1 < A.n_levels && s >= A.slab_base[k + 1]) ++k;
+    return A.cnt_off[k] + (s - A.slab_base[k]) * A.cnt_stride[k];
+}
+
+template <class PA>
 __device__ __forceinline__ float plane_at(PA &A, int k, int d, int m) {
     return slot_value(A, k, d, m, nullptr);
 }
@@ -1117,7 +1117,7 @@ __device__ __forceinline__ void peak_count_wave(PA &A, int w, int lane) {
     int64_t total = 0;
     for (int64_t sb = sbeg; sb < send; sb += 64) {
         const int64_t s = sb + lane;
-        const uint32_t c = (s < send) ? A.slab_cnt[s] : 0u;
+        const uint32_t c = (s < send) ? A.slab_cnt[slab_cnt_index(A, s)] : 0u;
         if (s < send && c == 0) A.surv[s] = 0;
         uint64_t nz = __ballot(c != 0);
         while (nz) {
@@ -1149,7 +1149,10 @@ __device__ __forceinline__ void peak_count_wave(PA &A, int w, int lane) {
                     bool ok = false;
                     if (m < p.mhi && slot_kept(A, p.k, p.d, m)) {
                         if (A.amask) {
-                            ok = slot_above(A, p.k, p.d, m) && peak_test_rec(A, p.k, p.d, m);
+                            if (slot_above(A, p.k, p.d, m)) {
+                                const float y = plane_at(A, p.k, p.d, m);
+                                ok = (y > A.threshold) && peak_test_rec(A, p.k, p.d, m, true, y);
+                            }
                         } else {
                             const float y = plane_at(A, p.k, p.d, m);
                             ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
@@ -1238,7 +1241,7 @@ __device__ __forceinline__ void peak_scatter_wave(PA &A, int w, int lane) {
             nz &= nz - 1;
             const int64_t ss = sb + l;
             const uint32_t nsurv = (uint32_t)__shfl((int)sv, l);
-            const uint32_t cc = A.slab_cnt[ss];
+            const uint32_t cc = A.slab_cnt[slab_cnt_index(A, ss)];
             const SlabPos p = slab_decode(A, ss);
             if (cc <= (uint32_t)A.slab_cap) {
                 const uint64_t msk = A.mask[ss];
@@ -1257,8 +1260,10 @@ __device__ __forceinline__ void peak_scatter_wave(PA &A, int w, int lane) {
                     int w = 0;
                     if (m < p.mhi && slot_kept(A, p.k, p.d, m)) {
                         if (A.amask) {
-                            ok = slot_above(A, p.k, p.d, m) && peak_test_rec(A, p.k, p.d, m);
-                            if (ok) y = slot_value(A, p.k, p.d, m, &w);
+                            if (slot_above(A, p.k, p.d, m)) {
+                                y = slot_value(A, p.k, p.d, m, &w);
+                                ok = (y > A.threshold) && peak_test_rec(A, p.k, p.d, m, true, y);
+                            }
                         } else {
                             y = slot_value(A, p.k, p.d, m, &w);
                             ok = (y > A.threshold) && peak_test(A, p.k, p.d, m, y);
