@@ -975,6 +975,59 @@ __device__ __noinline__ float rec_slot(const RecStep &R, int d, int j, int64_t m
     return best;
 }
 
+// Y of the slots m0, m0+1, m0+2 of level j in row d whose bit in `need` (bit i: slot m0+i) is
+// set, into y[i]: each unit of the level is formed once and added, in order, to the running sum
+// of every slot that covers it, so every slot's sum and SNR are those rec_slot forms.
+__device__ __noinline__ void rec_slots3(const RecStep &R, int d, int j, int64_t m0, int need,
+                                       float y[3]) {
+    const float *inr = R.in + (int64_t)d * R.ld_in;
+    float mu = 0.0f, inv = 1.0f;
+    if (R.normalise) {
+        mu = R.mean[d];
+        inv = 1.0f / R.sigma[d];
+    }
+    const RecLevel &L = R.lv[j];
+    float X[3] = {0.0f, 0.0f, 0.0f}, best[3];
+    int64_t room[3];
+    for (int i = 0; i < 3; ++i) {
+        best[i] = SPD_NEG_INF;
+        room[i] = 0;
+        if (!((need >> i) & 1)) continue;                   // (m0 + i may be -1 then)
+        room[i] = (int64_t)R.n_in - ((m0 + i) << L.k);
+        if (R.carry && (j > 0 || R.cin != nullptr)) {
+            const int64_t m = m0 + i, p0 = m << j;
+            if (R.cin && p0 < R.lv[0].slots) X[i] = R.cin[(int64_t)d * R.ld_cin + p0];
+            for (int l = 0; l < j; ++l) {
+                const int64_t p = m << (j - l);
+                const int uf = R.lv[l].ufull;
+                for (int u = 0; u < uf; ++u) X[i] += rec_unit(R, inr, mu, inv, l, p + u);
+            }
+        }
+    }
+    const float *rr = R.rho ? R.rho + (int64_t)d * R.ld_rho : nullptr;
+    const int first = (need & 1) ? 0 : (need & 2) ? 1 : 2;
+    const int last = (need & 4) ? 2 : (need & 2) ? 1 : 0;
+    for (int v = first; v < L.umax + last; ++v) {           // unit m0 + v
+        const float yu = rec_unit(R, inr, mu, inv, j, m0 + v);
+        for (int i = first; i <= last; ++i) {
+            const int u = v - i;                            // width index of slot m0 + i
+            if (!((need >> i) & 1) || u < 0 || u >= L.umax) continue;
+            X[i] += yu;
+            if ((L.evalmask >> u) & 1ull) {
+                float r = L.rt[u];
+                if (rr) {
+                    const double Lw = (double)L.base + ldexp((double)(u + 1), L.k);
+                    r = (float)((double)L.rt[u] / rho_of_width(rr, R.n_rho, Lw));
+                }
+                float val = X[i] * r;
+                if ((int64_t)L.base + ((int64_t)(u + 1) << L.k) > room[i]) val = SPD_NEG_INF;
+                if (val > best[i]) best[i] = val;
+            }
+        }
+    }
+    for (int i = 0; i < 3; ++i) y[i] = best[i];
+}
+
 // The helpers take the arguments either from the launch (one beam) or from a per-beam table in
 // the constant address space (a batch); PA is the (qualified) PeakArgs type.
 // SNR (and width, if w) of slot m of level k in row d: from the planes, or formed again.
@@ -1013,14 +1066,22 @@ __device__ __forceinline__ bool slot_above(PA &A, int k, int d, int m) {
 }
 
 // The 3x3 test when the planes are not stored: a neighbour at or below the threshold cannot
-// block a slot above it, so only neighbours whose group bit is set are formed again (and the
-// slot itself, once, if any is; y_known: its value is already in y).
+// block a slot above it, so only neighbours whose group bit is set are formed again, with the
+// slot itself if any is (y_known: its value is already y_in); the slots of one row are formed
+// together.
+// time_tested: m is a pre-candidate, so the cascade already compared it exactly with its time
+// neighbours that lie in the same wave's 256 slots of the tile (only those across a wave or
+// tile edge are unknown to it).
 template <class PA>
 __device__ __forceinline__ bool peak_test_rec(PA &A, int k, int d, int m, bool y_known = false,
-                                              float y_in = 0.0f) {
+                                              float y_in = 0.0f, bool time_tested = false) {
     const int slots = A.level_slots[k];
-    bool have = y_known;
-    float y = y_in;
+    const int ts = A.tile_slots[k];
+    const int lm = m - (m / ts) * ts;                     // slot within its tile
+    const bool left_known = time_tested && (lm & 255) != 0;
+    const bool right_known = time_tested && ((lm + 1) & 255) != 0 && lm + 1 < ts;
+    int need[3] = {0, 0, 0};
+    bool any = false;
 #pragma unroll
     for (int a = -1; a <= 1; ++a) {
         const int dn = d + a;
@@ -1028,18 +1089,33 @@ __device__ __forceinline__ bool peak_test_rec(PA &A, int k, int d, int m, bool y
 #pragma unroll
         for (int b = -1; b <= 1; ++b) {
             if (a == 0 && b == 0) continue;
+            if (a == 0 && ((b < 0 && left_known) || (b > 0 && right_known))) continue;
             const int mn = m + b;
             if (mn < 0 || mn >= slots) continue;
-            if (!slot_above(A, k, dn, mn)) continue;
-            if (!have) {
-                y = slot_value(A, k, d, m, nullptr);
-                have = true;
+            if (slot_above(A, k, dn, mn)) {
+                need[a + 1] |= 1 << (b + 1);
+                any = true;
             }
-            const float yn = slot_value(A, k, dn, mn, nullptr);
-            const bool earlier = (a < 0) || (a == 0 && b < 0);
-            if (earlier ? !(y > yn) : !(y >= yn)) return false;
         }
     }
+    if (!any) return true;
+    const RecStep &R = A.rec[A.level_step[k]];
+    const int j = A.level_j[k];
+    float y = y_in;
+    if (!y_known) need[1] |= 2;                 // the slot itself, formed with its row
+    float v[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (need[a]) rec_slots3(R, d + a - 1, j, (int64_t)m - 1, need[a], v[a]);
+    if (!y_known) y = v[1][1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (!((need[a] >> b) & 1) || (a == 1 && b == 1)) continue;
+            const bool earlier = (a < 1) || (a == 1 && b < 1);
+            if (earlier ? !(y > v[a][b]) : !(y >= v[a][b])) return false;
+        }
     return true;
 }
 
@@ -1136,7 +1212,8 @@ __device__ __forceinline__ void peak_count_wave(PA &A, int w, int lane) {
                     A.slab_ent[ss * A.slab_cap + lane] = key;
                     const int m = (int)key;
                     if (A.amask)
-                        ok = slot_kept(A, p.k, p.d, m) && peak_test_rec(A, p.k, p.d, m);
+                        ok = slot_kept(A, p.k, p.d, m) &&
+                             peak_test_rec(A, p.k, p.d, m, false, 0.0f, true);
                     else
                         ok = slot_kept(A, p.k, p.d, m) &&
                              peak_test(A, p.k, p.d, m, plane_at(A, p.k, p.d, m));
