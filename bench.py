@@ -1098,8 +1098,8 @@ def gated_beam(args, dev, net) -> dict:
     # window [start - L_end, start + width) of its row (lossy planes on unflagged tiles, the
     # exhaustive plane on flagged tiles), against the exhaustive search's best there
     fl_dev = gs.flag
-    def window_best(d, a, b):
-        tiles_c = fl_dev[d // 64]                                  # flags of the row's tiles
+    def window_best(d, a, b, gated=True):
+        tiles_c = fl_dev[d // 64] if gated else torch.zeros_like(fl_dev[d // 64])
         Ye, _ = gs.out.exh.level(0)
         s = torch.arange(a, b, device=dev)
         v = torch.where(tiles_c[s // 4096] != 0, Ye[d, a:b], torch.tensor(float("-inf"), device=dev))
@@ -1117,6 +1117,7 @@ def gated_beam(args, dev, net) -> dict:
         return best
     wins = [(p.dm, max(0, p.start - w.l_end), min(w.n, p.start + p.width)) for p in w.pulses]
     gbest = torch.stack([window_best(d, a, b) for d, a, b in wins]).cpu().numpy()
+    lbest = torch.stack([window_best(d, a, b, gated=False) for d, a, b in wins]).cpu().numpy()
     tiles = sorted({(p.dm // 64, min(63, (p.start + p.width // 2) // 4096)) for p in w.pulses})
     rt, ct = np.array(tiles).T
     del gs
@@ -1133,12 +1134,15 @@ def gated_beam(args, dev, net) -> dict:
     torch.cuda.empty_cache()
     sel = ebest > w.threshold
     loss = 1.0 - gbest[sel] / ebest[sel]
+    loss_l = 1.0 - lbest[sel] / ebest[sel]
     out = {"tiles": 4096, "pulse_tiles": len(tiles), "flag_rate": float(flag.mean()),
            "pulse_tiles_flagged": float(flag[rt, ct].mean()),
            "ms_propose": round(t_prop, 3), "ms_gated_total": round(t_all, 3),
            "ms_exhaustive": round(t_exh, 3), "speedup_vs_exhaustive": round(t_exh / t_all, 2),
            "pulses_detected_by_exhaustive": int(sel.sum()),
            "mean_loss_pulses": float(loss.mean()), "max_loss_pulses": float(loss.max()),
+           "mean_loss_pulses_lossy_alone": float(loss_l.mean()),
+           "max_loss_pulses_lossy_alone": float(loss_l.max()),
            "note": "network trained on L_end-256 tiles (boxcar pulses of width 1-64); applied "
                    "unchanged to the beam's Gaussian pulses at L_end 8192"}
     log(f"[bench] gated on the beam: {t_all:.1f} ms (propose {t_prop:.2f}) vs exhaustive "
