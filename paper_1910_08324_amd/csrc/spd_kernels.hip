@@ -320,6 +320,10 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
             }
         }
     }
+    // carried prefixes: BoxDIT families always, IGRID families never (known at compile time, so
+    // their code and branches vanish), the generic kernel as the launch says
+    constexpr int kCarry = (FAM >= 4 && FAM <= 6) ? 1 : (FAM == 0 ? -1 : 0);
+    const bool carry = kCarry < 0 ? (A.carry != 0) : (kCarry == 1);
     const int64_t u0 = (int64_t)tile * T;
     if (tid < kStepMaxLevels) st_cnt[tid] = 0;
     if (d == 0 && tile == 0 && V.rec()) write_rec<NTH>(A, V, V.rec());
@@ -379,7 +383,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
                 *reinterpret_cast<float4 *>(y0 + i) = w;
             }
         }
-        if (!FIRST && A.carry && V.cin()) {
+        if (!FIRST && carry && V.cin()) {
             const float *cr = V.cin() + (int64_t)d * V.ld_cin();
             float *c0 = lds + A.lv[0].lds_c;
             for (int i = tid; i < T; i += NTH) {
@@ -409,9 +413,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         const int ngroups = Sj / kGroup;
         const float *yj = ybuf;
         const float *cj = cbuf;
-        const bool has_carry = A.carry && (j > 0 || V.cin() != nullptr);
-        const bool to_lds = A.carry && (j + 1 < A.J);
-        const bool to_glb = A.carry && (j + 1 == A.J) && A.has_out;
+        const bool has_carry = carry && (j > 0 || V.cin() != nullptr);
+        const bool to_lds = carry && (j + 1 < A.J);
+        const bool to_glb = carry && (j + 1 == A.J) && A.has_out;
         float *cg = to_glb ? V.cout() + (int64_t)d * V.ld_out() + (int64_t)tile * (T >> A.J) : nullptr;
         const bool sync_batches = form_next || to_lds;   // a batch writes into the live buffers
         const int k = L.k;
