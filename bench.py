@@ -692,9 +692,11 @@ def hbm_section(dev, x) -> dict:
 
 def msd_section(args, dev, x, w) -> dict:
     """Noise statistics of the beam (spd_msd): mean and sigma per DM row with iterative
-    rejection, and sigma of every power-of-two decimation up to L_end.  Each pass reads the
-    row's samples once; the kernel reports how many passes each row took, so the algorithmic
-    bytes are 4 B x samples x passes."""
+    rejection, and sigma of every power-of-two decimation up to L_end.  The first pass reads the
+    row's samples; later passes need only the values listed beyond the band (a row is read again
+    only when the band stops being covered), so the algorithmic bytes are one read of the samples
+    (4 B each).  The method's FP64 work, every value tested and summed in every pass, is reported
+    beside it as the rate a kernel reading every value in every pass would have to reach."""
     import torch
     from paper_1910_08324_amd import msd as M
 
@@ -711,28 +713,26 @@ def msd_section(args, dev, x, w) -> dict:
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    nbytes = float(passes.sum().item()) * w.n * 4
+    nbytes = float(w.n_dm) * w.n * 4
     gbs = nbytes / (ms * 1e-3) / 1e9
     vals_per_sample = sum(1.0 / (1 << k) for k in range(levels))
-    alg_ops = 5.0 * vals_per_sample * float(passes.sum().item()) * w.n
+    # per value of every level: the difference from the shift, the |d| <= limit test, the kept
+    # select, the sum and the sum of squares (5 FP64 operations); about 2 values per sample
+    method_ops = 5.0 * vals_per_sample * float(passes.sum().item()) * w.n
     res = {"levels": levels, "tau": args.msd_tau, "max_iter": args.msd_iter, "ms": round(ms, 4),
            "dm_samples_per_s": w.n_dm * w.n / (ms * 1e-3),
            "passes_mean": round(float(passes.mean().item()), 3),
            "passes_max": int(passes.max().item()),
-           # bound by FP64 vector issue (SQ counters on this beam: the SIMDs issue a VALU
-           # instruction in 71% of cycles).  Algorithmic FP64 work: per value of every level
-           # the difference from the shift, the |d| <= limit test, the kept select, the sum and
-           # the sum of squares (5 operations); the levels hold about 2 values per sample.
-           # Peak: 256 CUs x 64 FP64 lanes x 2.4 GHz (78.6 TFLOP/s counting an FMA as 2).
-           "roofline": {"bound": "alu", "unit": "T FP64 op/s",
-                        "achieved": round(alg_ops / (ms * 1e-3) / 1e12, 3),
-                        "peak": FP64_LANE_PEAK_TOPS,
-                        "frac": round(alg_ops / (ms * 1e-3) / 1e12 / FP64_LANE_PEAK_TOPS, 4),
-                        "algorithmic_ops": alg_ops,
-                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                        "algorithmic_bytes": nbytes, "kernel": "spdm::msd_kernel"}}
+           "roofline": {"bound": "hbm", "unit": "GB/s", "achieved": round(gbs, 1),
+                        "peak": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "algorithmic_bytes": nbytes, "kernel": "spdm::msd_kernel",
+                        "note": "one read of the samples; the rejection passes after the first "
+                                "read only the values listed beyond the band",
+                        "method_fp64_ops": method_ops,
+                        "method_fp64_tops": round(method_ops / (ms * 1e-3) / 1e12, 3),
+                        "fp64_peak_tops": FP64_LANE_PEAK_TOPS}}
     log(f"[bench] msd: {ms:.3f} ms for {w.n_dm} x {w.n}, {levels} levels, {res['passes_mean']} "
-        f"passes per row on average: {gbs:.0f} GB/s of sample reads ({gbs / HBM_PEAK_GBS:.3f} of HBM)")
+        f"passes per row on average: {gbs:.0f} GB/s of samples ({gbs / HBM_PEAK_GBS:.3f} of HBM)")
     return res
 
 

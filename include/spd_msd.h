@@ -37,11 +37,17 @@ int spd_msd_workspace(int32_t n_dm, int32_t n_in, int32_t levels, int64_t *bytes
  * spd_msd: x [n_dm][ld] float (ld >= n_in); levels 1..SPD_MAX_LEVELS with n_in >> (levels-1)
  * >= 2; tau > 0; max_iter >= 0.  Outputs (device): mean[n_dm], sigma[n_dm] (float, level 0,
  * ready for spd_search), and, if not NULL, rho[n_dm][levels] and level_sd[n_dm][levels] (float)
- * and passes[n_dm] (int32: estimate passes over the row, 1 + the most rejection passes any level
- * took, at most 1 + max_iter; each pass reads the row's samples once).  The workspace holds the
- * decimated values of levels 9 and up (fewer than n_in / 256 per row).  One work-group per row;
- * asynchronous on the stream.  SPD_EINVAL for bad sizes or NULL mean / sigma, SPD_EWORKSPACE /
- * SPD_EALIGN for a short or unaligned (256-byte) workspace, SPD_EHIP for a failed launch.
+ * and passes[n_dm] (int32: estimate passes, 1 + the most rejection passes any level took, at most
+ * 1 + max_iter).  The first pass reads the row's samples and lists, per level 0..5, the values
+ * beyond a band around a pre-estimate of the mean (from a few tiles of the row); while the
+ * current limit covers that band, a rejection pass needs only the listed values, otherwise it
+ * reads the row again and lists anew.  The kept sets, counts and passes are those of passes that
+ * read every value; only the order of the FP64 sums differs, and it is fixed (results do not vary
+ * from run to run).  The workspace holds, per row, the decimated values of levels 6 and up (fewer
+ * than n_in / 32) and room for the lists (1/16 of the values of each level 0..5); its size
+ * depends on n_in only.  One work-group per row; asynchronous on the stream.  SPD_EINVAL for bad
+ * sizes or NULL mean / sigma, SPD_EWORKSPACE / SPD_EALIGN for a short or unaligned (256-byte)
+ * workspace, SPD_EHIP for a failed launch.
  */
 int spd_msd(const float *x, int64_t ld, int32_t n_dm, int32_t n_in, int32_t levels, float tau,
             int32_t max_iter, float *mean, float *sigma, float *rho, float *level_sd,

@@ -12,8 +12,18 @@
 // square, with the shift the level's current mean estimate; after the pass the threads' partial
 // statistics (count, mean, sum of squared deviations) are merged pairwise with Chan, Golub &
 // LeVeque's formula in a fixed order.  Levels 0..2, which every lane serves, count their kept
-// values per wave instead, and their lanes' sums around the common shift are totalled directly.  Levels converge independently; the row's passes stop
-// when every level has.
+// values per wave instead, and their lanes' sums around the common shift are totalled directly.
+// Levels converge independently; the row's passes stop when every level has.
+//
+// Later passes need not read the row.  A "build" pass (a full read with rejection) also lists,
+// per level, every value farther than 0.9 of the current limit from the current mean, and keeps
+// the count and sums of the values it did not list.  While the limit of a later pass still
+// covers the whole unlisted band (|value - list centre| <= list threshold implies
+// |value - mean| <= limit, checked with a margin for rounding), every unlisted value is kept, so
+// the pass needs only the listed values: it tests them exactly as a full read would and adds
+// the unlisted statistics.  The kept sets, hence the counts, pass counts and stopping decisions,
+// are those of full reads; only the order of the FP64 sums differs.  When the band is no longer
+// covered, or a list overflowed its room, the next pass is a build pass again.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -27,9 +37,29 @@
 namespace spdm {
 
 constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
 constexpr int kTile = 4 * kThreads;   // samples per tile
 constexpr int kRegLevels = 9;          // levels 0..8 formed in registers
-constexpr int kWsFirst = 9;            // levels 9.. live in the workspace
+constexpr int kListLevels = 6;         // levels 0..5 are summed as the row streams by
+constexpr int kArrFirst = 6;           // levels 6.. are stored whole by the first pass
+constexpr double kListFrac = 0.8;      // a rebuild lists values beyond 0.8 of the limit
+constexpr int kProbeTiles = 8;         // tiles of the pre-estimate, spread over the row
+
+// Per row, the workspace holds the values of levels 6.. (level 6 first, then 7, ...; fewer than
+// n / 32 in all), then for each level k < 6 one list per wave with room for 1/16 of the wave's
+// values of the level, plus 16.
+__host__ __device__ inline int64_t arr_offset(int n, int k) {   // of level k >= 6
+    int64_t o = 0;
+    for (int i = kArrFirst; i < k; ++i) o += (int64_t)(n >> i);
+    return o;
+}
+__host__ __device__ constexpr int list_room(int n, int k) { return ((n >> k) >> 6) + 16; }
+__host__ __device__ inline int64_t list_offset(int n, int k) {   // of level k's first list
+    int64_t o = (int64_t)(n >> 5) + 8;
+    for (int i = 0; i < k; ++i) o += (int64_t)kWaves * list_room(n, i);
+    return o;
+}
+__host__ __device__ inline int64_t ws_row_doubles(int n) { return list_offset(n, kListLevels); }
 
 struct Part {
     double n, mean, m2;
@@ -108,14 +138,24 @@ struct Level {
     double shift;       // subtracted before summing
     double m, lim;      // a value is kept in a rejection pass if |value - m| <= lim
     double sd, kept;
+    double lc, lt;      // last full read: values with |value - lc| > lt are listed
+    double nn, ns1, ns2;  // the unlisted values: count and sums of (value - lc) and its square
     int active;         // still being refined
     int iters;          // rejection passes that changed the estimate
+    int listed;         // the lists hold every value beyond lt (none overflowed)
 };
+
+// every unlisted value is kept by a pass with this level's current mean and limit: the band
+// |v - lc| <= lt lies inside |v - m| <= lim with room for the rounding of both differences
+__device__ __forceinline__ bool band_covered(const Level &L) {
+    const double slack = 1e-12 * (L.lim + L.lt + fabs(L.lc) + fabs(L.m));
+    return L.listed && L.lt + fabs(L.lc - L.m) + slack <= L.lim;
+}
 
 struct MsdArgs {
     const float *x;
     int64_t ld;
-    double *ws;          // per row: the values of levels 9.. (n >> 9 of level 9, then level 10, ...)
+    double *ws;          // per row: the values of levels 6.., then the lists of levels 0..5
     int64_t ws_row;      // doubles per row
     float *mean, *sigma, *rho, *level_sd;
     int32_t *passes;
@@ -176,23 +216,45 @@ __device__ __forceinline__ void level_step(double &v, double *slots, int lane, i
         slots[kSlotK + (lane >> (K - 2))] = (FULL || s + (1 << K) <= n) ? v : __builtin_nan("");
 }
 
+// lanes below this one
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
+
+// append the values of the lanes whose `far` is set to the wave's list, in lane order after the
+// values appended before (a full list still counts them, which marks the overflow)
+__device__ __forceinline__ void list_append(bool far, double v, double *list, int &cnt, int room,
+                                            int lane) {
+    const uint64_t b = __ballot(far);
+    if (b) {
+        const int i = cnt + __popcll(b & lanes_below(lane));
+        if (far && i < room) list[i] = v;
+        cnt += __popcll(b);
+    }
+}
+
 // take for a level every lane of the wave serves: the count of kept values is kept per wave
-// (a ballot's population count, on the scalar unit) instead of per lane
+// (a ballot's population count, on the scalar unit) instead of per lane.  LIST: values beyond
+// the list threshold also go to the wave's list of the level.
+template <bool LIST>
 __device__ __forceinline__ void take_w(Acc &a, uint32_t &nw, const Level &L, bool first,
-                                       bool valid, double v) {
+                                       bool valid, double v, double *list, int &cnt, int room,
+                                       int lane) {
     const double d = v - L.shift;
     const bool ok = valid && (first || fabs(d) <= L.lim);
     const double e = ok ? d : 0.0;           // (d may be NaN for a value past the data)
     nw += (uint32_t)__popcll(__ballot(ok));
     a.s1 += e;
     a.s2 = fma(e, e, a.s2);
+    if (LIST) list_append(valid && !(fabs(d) <= L.lt), v, list, cnt, room, lane);   // lc == shift
 }
 
 // statistics of a level all of whose values share one shift: the work-group's totals of the
-// lanes' sums and the waves' counts give the mean and the sum of squared deviations
-__device__ __forceinline__ Part wave_counted_part(const Acc &a, uint32_t nw, double shift, Part *sh) {
+// lanes' sums and the waves' counts give the mean and the sum of squared deviations (`tot`
+// receives the totals: count and the sums of (value - shift) and its square)
+__device__ __forceinline__ Part wave_counted_part(const Acc &a, uint32_t nw, double shift, Part *sh,
+                                                  Part *tot = nullptr) {
     Part p = {(threadIdx.x & 63) == 0 ? (double)nw : 0.0, a.s1, a.s2};
     const Part t = block_sums(p, sh);
+    if (tot) *tot = t;
     Part u = {0.0, 0.0, 0.0};
     if (t.n > 0.0) {
         u.n = t.n;
@@ -202,20 +264,21 @@ __device__ __forceinline__ Part wave_counted_part(const Acc &a, uint32_t nw, dou
     return u;
 }
 
-__global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
+__global__ __launch_bounds__(kThreads, 4) void msd_kernel(const MsdArgs A) {
     __shared__ Part sh[4];
     __shared__ Level lv[SPD_MAX_LEVELS];
     __shared__ double t8[4];                   // level-8 value of each wave in the current tile
     __shared__ double slot_buf[4][64];         // per wave: this tile's level 3..8 values
-    __shared__ int any_active;
+    __shared__ int list_cnt[kWaves][kListLevels];  // values each wave listed in the last full read
+    __shared__ int any_active, pass_mode;
     const int d = blockIdx.x;
     if (d >= A.n_dm) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform over the wave
     const int n = A.n_in;
     const int K = A.levels;
-    const int kreg = min(K, kRegLevels);
+    const int klist = min(K, kListLevels);
     const float *xr = A.x + (int64_t)d * A.ld;
     double *wr = A.ws + (int64_t)d * A.ws_row;
     const int n_tiles = (n + kTile - 1) / kTile;
@@ -226,37 +289,66 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
                                                                                    : lane < 63 ? 8 : kRegLevels;
     double *slots = slot_buf[wave];
     slots[63] = __builtin_nan("");               // lane 63 has no value
+    // this wave's list of level k
+    auto list_of = [&](int k) { return wr + list_offset(n, k) + (int64_t)wave * list_room(n, k); };
 
     if (tid < K) {
         Level &L = lv[tid];
-        L.shift = (double)xr[0] * (double)(1 << tid);   // first pass: a value of the right size
+        L.shift = (double)xr[0] * (double)(1 << tid);   // pre-estimate: a value of the right size
         L.m = 0.0;
         L.lim = 0.0;
         L.sd = 0.0;
         L.kept = 0.0;
+        L.lc = L.shift;
+        L.lt = 0.0;
+        L.nn = L.ns1 = L.ns2 = 0.0;
         L.active = 1;
         L.iters = 0;
+        L.listed = 0;
     }
     __syncthreads();
 
-    int pass = 0;
+    // Kinds of pass: the pre-estimate (mean and sd of a few tiles spread over the row, which
+    // centre the first pass's lists and set their band), a full read (the first estimate, or a
+    // rejection pass, both listing the values beyond the band), a list pass (the listed values
+    // only).  The pre-estimate counts as no pass.
+    enum { kProbe = 0, kRead = 1, kList = 2 };
+    const int n_probe = min(n_tiles, kProbeTiles);
+    int pass = -1;
     for (; pass <= A.max_iter; ++pass) {
-        const bool first = pass == 0;
-        if (!first) {
-            if (tid == 0) {
-                int a = 0;
-                for (int k = 0; k < K; ++k) a |= lv[k].active;
-                any_active = a;
+        const bool probe = pass < 0;
+        const bool first = pass <= 0;            // every valid value is kept
+        if (tid == 0) {
+            int a = 0;
+            bool lists = pass > 0;
+            for (int k = 0; k < K; ++k) a |= lv[k].active;
+            for (int k = 0; k < klist; ++k)
+                if (lv[k].active) lists = lists && band_covered(lv[k]);
+            const int mode = probe ? kProbe : lists ? kList : kRead;
+            if (mode == kRead && pass > 0) {
+                for (int k = 0; k < klist; ++k) {
+                    Level &L = lv[k];
+                    L.lc = L.shift;                 // the current mean
+                    L.lt = kListFrac * L.lim;
+                }
             }
-            __syncthreads();
-            if (!any_active) break;
+            any_active = pass <= 0 ? 1 : a;
+            pass_mode = mode;
         }
-        // the samples are read again only while a level formed from them in registers is open
-        // (levels 9.. come from the workspace after the first pass)
+        __syncthreads();
+        if (!any_active) break;
+        const int mode = pass_mode;
+        const bool build = mode == kRead;
+        // the samples are read again only while a level of 0..5 is open and its listed values do
+        // not suffice (levels 6.. come from the workspace after the first pass)
         bool read_row = first;
-        for (int k = 0; k < kreg; ++k) read_row = read_row || lv[k].active;
+        for (int k = 0; k < klist; ++k) read_row = read_row || lv[k].active;
+        read_row = read_row && mode != kList;
         Acc a0, a1, a2, am;                      // levels 0, 1, 2 and this lane's level of 3..8
         uint32_t n0w = 0, n1w = 0, n2w = 0;      // the wave's kept counts of levels 0, 1, 2
+        int lc_[kListLevels];                    // the wave's listed counts (full read)
+#pragma unroll
+        for (int k = 0; k < kListLevels; ++k) lc_[k] = 0;
         acc_reset(a0);
         acc_reset(a1);
         acc_reset(a2);
@@ -268,12 +360,16 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
         const bool on0 = first || L0.active;
         const bool on1 = K > 1 && (first || L1.active);
         const bool on2 = K > 2 && (first || L2.active);
-        const bool onm = my_k < kreg && (first || Lm.active);
+        const bool onm = my_k < klist && (first || Lm.active);   // lanes of levels 3..5
+        const bool arr = pass == 0 && my_k >= kArrFirst && my_k < K;   // lanes of 6..8
 
         auto fetch = [&](int tile, float4 &f) {
             const int s = tile * kTile + 4 * tid;
             if (vec && s + 3 < n) {
-                f = *reinterpret_cast<const float4 *>(xr + s);
+                // streamed once per full read: keep the cache for the lists being written
+                typedef float v4f __attribute__((ext_vector_type(4)));
+                const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(xr + s));
+                f = make_float4(t.x, t.y, t.z, t.w);
             } else {
                 f.x = s + 0 < n ? xr[s + 0] : 0.0f;
                 f.y = s + 1 < n ? xr[s + 1] : 0.0f;
@@ -281,25 +377,35 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
                 f.w = s + 3 < n ? xr[s + 3] : 0.0f;
             }
         };
+        // the pre-estimate reads tiles (i n_tiles) / n_probe, a full read every tile
+        auto tile_at = [&](int i) { return probe ? (int)(((int64_t)i * n_tiles) / n_probe) : i; };
+        const int n_read = probe ? n_probe : n_tiles;
         float4 nxt = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (read_row) fetch(0, nxt);
+        if (read_row) fetch(tile_at(0), nxt);
         // one tile; FULL: every sample of the tile is inside the data (all tiles but the last),
-        // so the per-value validity tests fold away
-        auto tile_body = [&](auto full_tag, int tile, float4 cur) {
+        // so the per-value validity tests fold away; LIST: the values beyond the band are listed
+        auto tile_body = [&](auto full_tag, auto list_tag, int tile, float4 cur) {
             constexpr bool FULL = decltype(full_tag)::value;
+            constexpr bool LIST = decltype(list_tag)::value;
             const int s = tile * kTile + 4 * tid;                // first sample of this thread
             const double v0[4] = {(double)cur.x, (double)cur.y, (double)cur.z, (double)cur.w};
             if (on0)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) take_w(a0, n0w, L0, first, FULL || s + q < n, v0[q]);
+                for (int q = 0; q < 4; ++q)
+                    take_w<LIST>(a0, n0w, L0, first, FULL || s + q < n, v0[q], list_of(0), lc_[0],
+                                 list_room(n, 0), lane);
             // levels 1, 2 within the thread
             const double v1a = v0[0] + v0[1], v1b = v0[2] + v0[3];
             if (on1) {
-                take_w(a1, n1w, L1, first, FULL || s + 2 <= n, v1a);
-                take_w(a1, n1w, L1, first, FULL || s + 4 <= n, v1b);
+                take_w<LIST>(a1, n1w, L1, first, FULL || s + 2 <= n, v1a, list_of(1), lc_[1],
+                             list_room(n, 1), lane);
+                take_w<LIST>(a1, n1w, L1, first, FULL || s + 4 <= n, v1b, list_of(1), lc_[1],
+                             list_room(n, 1), lane);
             }
             double v = v1a + v1b;
-            if (on2) take_w(a2, n2w, L2, first, FULL || s + 4 <= n, v);
+            if (on2)
+                take_w<LIST>(a2, n2w, L2, first, FULL || s + 4 <= n, v, list_of(2), lc_[2],
+                             list_room(n, 2), lane);
             // levels 3..8 across lanes: after step k, lane l holds the value of level k that starts
             // at its own samples when l is a multiple of 2^(k-2); holders park their values in the
             // wave's 64 slots (level k from slot 64 - 2^(9-k), one per holder, NaN past the data), and
@@ -310,37 +416,79 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
             level_step<6, FULL>(v, slots, lane, s, n);
             level_step<7, FULL>(v, slots, lane, s, n);
             level_step<8, FULL>(v, slots, lane, s, n);
+            bool far = false;
+            double mv = 0.0;
             if (onm) {
-                const double mv = slots[lane];                   // written by this wave above
-                take(am, Lm, first, FULL || !__builtin_isnan(mv), mv);
+                mv = slots[lane];                                // written by this wave above
+                const bool valid = FULL || !__builtin_isnan(mv);
+                take(am, Lm, first, valid, mv);
+                if (LIST) far = valid && !(fabs(mv - Lm.shift) <= Lm.lt);   // lc == shift
+            }
+            if (arr) {
+                // the first pass stores levels 6..8 whole: level k's values of a tile in wave,
+                // then lane order (lanes 56.., 60.., 62 hold levels 6, 7, 8)
+                const int k = my_k;
+                const int lane0 = k == 6 ? 56 : k == 7 ? 60 : 62;
+                const int64_t i = (int64_t)tile * (kTile >> k) + wave * (256 >> k) + (lane - lane0);
+                if (i < (n >> k)) wr[arr_offset(n, k) + i] = slots[lane];
+            }
+            if (LIST) {
+                // each level's lanes form one run of the wave: append level by level (the
+                // ballot and the counts stay in uniform control flow)
+                const uint64_t b = __ballot(far);
+                if (b) {
+#pragma unroll
+                    for (int k = 3; k < kListLevels; ++k) {
+                        const uint64_t run = k == 3 ? 0xffffffffull : k == 4 ? 0xffffull << 32
+                                                                    : 0xffull << 48;
+                        const uint64_t bk = b & run;
+                        if (bk) {
+                            const int i = lc_[k] + __popcll(bk & lanes_below(lane));
+                            if (far && my_k == k && i < list_room(n, k)) list_of(k)[i] = mv;
+                            lc_[k] += __popcll(bk);
+                        }
+                    }
+                }
             }
             // levels 9 and 10 (and the level-10 values the higher levels are built from): the
             // first pass writes them to the workspace
-            if (first && K > kWsFirst) {
+            if (pass == 0 && K > 9) {
                 if (lane == 0) t8[wave] = v;
                 __syncthreads();
                 if (tid == 0) {
                     const int64_t i9 = (int64_t)tile * 2;
                     const double a9 = t8[0] + t8[1], b9 = t8[2] + t8[3];
+                    double *w9 = wr + arr_offset(n, 9);
                     const int64_t n9 = n >> 9;
-                    if (i9 < n9) wr[i9] = a9;
-                    if (i9 + 1 < n9) wr[i9 + 1] = b9;
-                    if (K > 10 && tile < (n >> 10)) wr[n9 + tile] = a9 + b9;
+                    if (i9 < n9) w9[i9] = a9;
+                    if (i9 + 1 < n9) w9[i9 + 1] = b9;
+                    if (K > 10 && tile < (n >> 10)) w9[n9 + tile] = a9 + b9;
                 }
                 __syncthreads();
             }
         };
-        for (int tile = 0; read_row && tile < n_tiles; ++tile) {
+        for (int i = 0; read_row && i < n_read; ++i) {
+            const int tile = tile_at(i);
             const float4 cur = nxt;
-            if (tile + 1 < n_tiles) fetch(tile + 1, nxt);        // in flight while this tile computes
-            if ((tile + 1) * kTile <= n)                         // uniform over the work-group
-                tile_body(std::true_type{}, tile, cur);
-            else
-                tile_body(std::false_type{}, tile, cur);
+            if (i + 1 < n_read) fetch(tile_at(i + 1), nxt);      // in flight while this tile computes
+            const bool full = (tile + 1) * kTile <= n;            // uniform over the work-group
+            if (build) {
+                if (full)
+                    tile_body(std::true_type{}, std::true_type{}, tile, cur);
+                else
+                    tile_body(std::false_type{}, std::true_type{}, tile, cur);
+            } else {
+                if (full)
+                    tile_body(std::true_type{}, std::false_type{}, tile, cur);
+                else
+                    tile_body(std::false_type{}, std::false_type{}, tile, cur);
+            }
         }
-        if (first && K > 11) {
+        if (build && lane == 0)
+            for (int k = 0; k < klist; ++k) list_cnt[wave][k] = lc_[k];
+        if (pass == 0 && K > 11) {
             // levels 11.. from pairs of the level below, all in the workspace
-            int64_t off_prev = (int64_t)(n >> 9), off = off_prev + (n >> 10);
+            int64_t off_prev = arr_offset(n, 10), off = arr_offset(n, 11);
             for (int k = 11; k < K; ++k) {
                 const int64_t cnt = (int64_t)(n >> k);
                 for (int64_t i = tid; i < cnt; i += kThreads) wr[off + i] = wr[off_prev + 2 * i] + wr[off_prev + 2 * i + 1];
@@ -349,12 +497,23 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
                 __syncthreads();
             }
         }
+        __syncthreads();                          // list counts (and workspace levels) visible
 
         // merge the pass's statistics and update every level still being refined (the decision
         // to skip a level is uniform across the work-group)
         auto update_merged = [&](int k, const Part u) {
             if (tid == 0) {
                 Level &S = lv[k];
+                if (probe) {
+                    // centre and band of the first pass's lists: 0.9 of the limit the
+                    // pre-estimate gives, less by three standard errors of its sd
+                    const double sd = u.n > 1.0 ? sqrt(u.m2 / (u.n - 1.0)) : 0.0;
+                    const double frac = 0.9 / (1.0 + 3.0 / sqrt(fmax(2.0 * u.n, 1.0)));
+                    S.shift = u.n > 0.0 ? u.mean : S.shift;
+                    S.lc = S.shift;
+                    S.lt = frac * A.tau * sd;
+                    return;
+                }
                 if (first) {
                     S.m = u.mean;
                     S.sd = u.n > 1.0 ? sqrt(u.m2 / (u.n - 1.0)) : 0.0;
@@ -372,28 +531,115 @@ __global__ __launch_bounds__(kThreads) void msd_kernel(const MsdArgs A) {
                 S.lim = A.tau * S.sd;
                 S.shift = S.m;
             }
-            __syncthreads();
         };
-        auto update = [&](int k, Part p) { update_merged(k, block_merge(p, sh)); };
-        if (K > 0 && (first || lv[0].active)) update_merged(0, wave_counted_part(a0, n0w, lv[0].shift, sh));
-        if (K > 1 && (first || lv[1].active)) update_merged(1, wave_counted_part(a1, n1w, lv[1].shift, sh));
-        if (K > 2 && (first || lv[2].active)) update_merged(2, wave_counted_part(a2, n2w, lv[2].shift, sh));
-        for (int k = 3; k < kreg; ++k) {
-            if (first || lv[k].active) {
+        // the listed values of level k kept by the current estimate (every one in the first
+        // pass): totals of the count and of the sums of (value - centre) and its square, in a
+        // fixed order (the waves' lists in turn)
+        auto list_sums = [&](int k, double centre) {
+            const Level L = lv[k];
+            const int room = list_room(n, k);
+            Acc a;
+            acc_reset(a);
+            // the waves' lists one after another: entry j of the concatenation
+            const double *l = wr + list_offset(n, k);
+            const int c0 = min(list_cnt[0][k], room), c1 = min(list_cnt[1][k], room);
+            const int c2 = min(list_cnt[2][k], room), c3 = min(list_cnt[3][k], room);
+            const int p1 = c0, p2 = p1 + c1, p3 = p2 + c2, c = p3 + c3;
+            for (int j0 = 0; j0 < c; j0 += 4 * kThreads) {
+                double v[4];                     // four loads in flight, then their sums in order
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u * kThreads + tid;
+                    const int w = (j >= p1) + (j >= p2) + (j >= p3);
+                    const int base = w == 0 ? 0 : w == 1 ? p1 : w == 2 ? p2 : p3;
+                    v[u] = j < c ? l[(int64_t)w * room + (j - base)] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = j0 + u * kThreads + tid < c &&
+                                    (first || fabs(v[u] - L.shift) <= L.lim);
+                    const double e = ok ? v[u] - centre : 0.0;
+                    a.n += ok ? 1 : 0;
+                    a.s1 += e;
+                    a.s2 = fma(e, e, a.s2);
+                }
+            }
+            Part p = {(double)a.n, a.s1, a.s2};
+            return block_sums(p, sh);
+        };
+        // full read: the unlisted values' statistics are the kept totals less the listed kept
+        // values (all around the list centre)
+        auto keep_unlisted = [&](int k, const Part &tot) {
+            bool full = true;
+            for (int w = 0; w < kWaves; ++w) full = full && list_cnt[w][k] <= list_room(n, k);
+            Part ls = {0.0, 0.0, 0.0};
+            if (full) ls = list_sums(k, lv[k].lc);
+            if (tid == 0) {
+                Level &S = lv[k];
+                S.listed = full;
+                S.nn = tot.n - ls.n;
+                S.ns1 = tot.mean - ls.mean;
+                S.ns2 = tot.m2 - ls.m2;
+            }
+        };
+        // list pass: the unlisted statistics plus the listed values the estimate keeps
+        auto list_part = [&](int k) {
+            const Part ls = list_sums(k, lv[k].lc);
+            const Level &L = lv[k];
+            Part u = {0.0, 0.0, 0.0};
+            const double cnt = L.nn + ls.n;
+            if (cnt > 0.0) {
+                const double s1 = L.ns1 + ls.mean, s2 = L.ns2 + ls.m2;
+                u.n = cnt;
+                u.mean = L.lc + s1 / cnt;
+                u.m2 = fmax(0.0, s2 - s1 * (s1 / cnt));
+            }
+            return u;
+        };
+        for (int k = 0; k < klist; ++k) {
+            if (!(first || lv[k].active)) continue;
+            if (mode == kList) {
+                update_merged(k, list_part(k));
+            } else if (k < 3) {
+                const Acc &a = k == 0 ? a0 : k == 1 ? a1 : a2;
+                const uint32_t nw = k == 0 ? n0w : k == 1 ? n1w : n2w;
+                Part tot;
+                const Part u = wave_counted_part(a, nw, lv[k].shift, sh, &tot);
+                if (build) keep_unlisted(k, tot);
+                update_merged(k, u);
+            } else {
                 Part p = {0.0, 0.0, 0.0};
                 if (my_k == k) p = acc_part(am, lv[k].shift);
-                update(k, p);
+                const Part u = block_merge(p, sh);
+                if (build) {
+                    Part q = {0.0, 0.0, 0.0};
+                    if (my_k == k) q = Part{(double)am.n, am.s1, am.s2};
+                    keep_unlisted(k, block_sums(q, sh));
+                }
+                update_merged(k, u);
             }
+            __syncthreads();
         }
+        if (probe) continue;
         int64_t off = 0;
-        for (int k = kWsFirst; k < K; ++k) {
+        for (int k = kArrFirst; k < K; ++k) {
             const int64_t cnt = (int64_t)(n >> k);
             const Level Lk = lv[k];
             if (first || Lk.active) {
                 Acc a;
                 acc_reset(a);
-                for (int64_t i = tid; i < cnt; i += kThreads) take(a, Lk, first, true, wr[off + i]);
-                update(k, acc_part(a, Lk.shift));
+                for (int64_t i0 = 0; i0 < cnt; i0 += 4 * kThreads) {
+                    double v[4];                 // four loads in flight, then their sums in order
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t i = i0 + u * kThreads + tid;
+                        v[u] = i < cnt ? wr[off + i] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) take(a, Lk, first, i0 + u * kThreads + tid < cnt, v[u]);
+                }
+                update_merged(k, block_merge(acc_part(a, Lk.shift), sh));
+                __syncthreads();
             }
             off += cnt;
         }
@@ -420,8 +666,8 @@ int spd_msd_workspace(int32_t n_dm, int32_t n_in, int32_t levels, int64_t *bytes
     if (!bytes || n_dm < 1 || n_in < 2 || n_in > INT32_MAX - 4096 || levels < 1 ||
         levels > SPD_MAX_LEVELS || ((int64_t)n_in >> (levels - 1)) < 2)
         return SPD_EINVAL;
-    // levels 9.. of every row: fewer than n_in / 256 values
-    *bytes = (int64_t)n_dm * ((n_in >> 8) + 8) * 8 + 256;
+    // levels 9.. of every row (fewer than n_in / 256 values) and the lists of levels 0..8
+    *bytes = (int64_t)n_dm * spdm::ws_row_doubles(n_in) * 8 + 256;
     return SPD_OK;
 }
 
@@ -438,7 +684,7 @@ int spd_msd(const float *x, int64_t ld, int32_t n_dm, int32_t n_in, int32_t leve
     a.x = x;
     a.ld = ld;
     a.ws = static_cast<double *>(workspace);
-    a.ws_row = (n_in >> 8) + 8;
+    a.ws_row = spdm::ws_row_doubles(n_in);
     a.mean = mean;
     a.sigma = sigma;
     a.rho = rho;

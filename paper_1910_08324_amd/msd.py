@@ -25,7 +25,8 @@ def lib():
 def msd(x, levels: int, tau: float = 2.0, max_iter: int = 10, n_in=None, workspace=None,
         with_passes: bool = False):
     """(mean [n_dm], sigma [n_dm], rho [n_dm][levels], level_sd [n_dm][levels]) of the rows of
-    x (device float [n_dm][ld]); with_passes adds passes [n_dm] (int32, reads of each row)."""
+    x (device float [n_dm][ld]); with_passes adds passes [n_dm] (int32, estimate passes of each
+    row)."""
     import torch
     n_dm = x.shape[0]
     n_in = x.shape[1] if n_in is None else int(n_in)

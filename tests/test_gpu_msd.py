@@ -61,6 +61,51 @@ def test_msd_matches_oracle(M, n, levels, tau, max_iter):
     say(f"  rho of the MA(1) row: {np.round(rho[1], 3)}")
 
 
+def rows_for_lists(n, seed):
+    """Rows that take every route of the kernel's rejection passes: white noise (the later passes
+    use the lists of values beyond the band), heavy contamination (15% of the samples far out:
+    the band moves and the lists are rebuilt), a strong wide pulse (the pre-estimate may sit on
+    it), uniform noise and a slow trend."""
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal(n)
+    dirty = rng.standard_normal(n)
+    bad = rng.random(n) < 0.15
+    dirty[bad] += rng.choice([-1.0, 1.0], bad.sum()) * rng.uniform(4, 40, bad.sum())
+    pulse = rng.standard_normal(n)
+    pulse[n // 2: n // 2 + n // 6] += 6.0
+    uni = rng.uniform(-1.0, 1.0, n) + 3.0
+    trend = rng.standard_normal(n) + np.linspace(-4.0, 4.0, n)
+    return np.stack([white, dirty, pulse, uni, trend]).astype(np.float32)
+
+
+@pytest.mark.parametrize("tau", [1.0, 1.5, 2.0, 3.0])
+@pytest.mark.parametrize("n,levels", [(131072 + 777, 14), (20480, 9), (3000, 6)])
+def test_msd_rejection_routes(M, tau, n, levels):
+    """tau = 1 lists 40% of the values beyond the band (the lists overflow: every pass reads the
+    row); tau = 1.5, 2 shrink the limit pass after pass (the band stops being covered and the
+    lists are rebuilt); tau = 3 converges on the lists; the oracle decides every value the
+    same way, so the counts, passes and statistics agree."""
+    x = rows_for_lists(n, 7)
+    mean, sigma, rho, lsd, passes = M.msd(torch.from_numpy(x).cuda(), levels, tau=tau,
+                                          max_iter=12, with_passes=True)
+    mean, sigma, rho, lsd, passes = (t.cpu().numpy() for t in (mean, sigma, rho, lsd, passes))
+    for d in range(x.shape[0]):
+        r = om.msd_row(x[d], levels, tau=tau, max_iter=12)
+        assert passes[d] == max(r["passes"]), (d, passes[d], r["passes"])
+        assert mean[d] == pytest.approx(r["mean"][0], rel=1e-6, abs=1e-7), d
+        assert np.allclose(lsd[d], r["sd"], rtol=1e-6), d
+        assert np.allclose(rho[d], r["rho"], rtol=1e-6), d
+
+
+def test_msd_is_deterministic(M):
+    """The lists are filled and summed in a fixed order: two runs agree bit for bit."""
+    x = torch.from_numpy(rows_for_lists(65536 + 300, 9)).cuda()
+    a = M.msd(x, 12, tau=2.0, max_iter=10, with_passes=True)
+    b = M.msd(x, 12, tau=2.0, max_iter=10, with_passes=True)
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+
+
 @pytest.mark.parametrize("method,l_end", [("ig1", 700), ("bd16", 700), ("ig3", 300), ("exh", 300)])
 def test_search_with_sigma_table(M, method, l_end):
     from paper_1910_08324_amd import spd
