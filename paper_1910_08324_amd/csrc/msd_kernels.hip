@@ -112,6 +112,28 @@ __device__ Part block_sums(Part p, Part *sh) {
     return t;
 }
 
+// the same two reductions over one wave only (every lane receives the result)
+__device__ __forceinline__ Part wave_merge(Part p) {
+    for (int o = 1; o < 64; o <<= 1) {
+        Part q;
+        q.n = __shfl_xor(p.n, o);
+        q.mean = __shfl_xor(p.mean, o);
+        q.m2 = __shfl_xor(p.m2, o);
+        const bool upper = (threadIdx.x & o) != 0;
+        p = upper ? merge(q, p) : merge(p, q);
+    }
+    return p;
+}
+
+__device__ __forceinline__ Part wave_sums(Part p) {
+    for (int o = 1; o < 64; o <<= 1) {
+        p.n += __shfl_xor(p.n, o);
+        p.mean += __shfl_xor(p.mean, o);
+        p.m2 += __shfl_xor(p.m2, o);
+    }
+    return p;
+}
+
 // a thread's running sums of one level: count, sum and sum of squares of (value - shift)
 struct Acc {
     int n;
@@ -162,6 +184,37 @@ struct MsdArgs {
     int32_t n_dm, n_in, levels, max_iter;
     double tau;
 };
+
+// a level's estimate after a pass with statistics u (one thread)
+__device__ __forceinline__ void update_level(Level &S, const Part &u, bool probe, bool first,
+                                             const MsdArgs &A) {
+    if (probe) {
+        // centre and band of the first pass's lists: 0.9 of the limit the pre-estimate gives,
+        // less by three standard errors of its sd
+        const double sd = u.n > 1.0 ? sqrt(u.m2 / (u.n - 1.0)) : 0.0;
+        const double frac = 0.9 / (1.0 + 3.0 / sqrt(fmax(2.0 * u.n, 1.0)));
+        S.shift = u.n > 0.0 ? u.mean : S.shift;
+        S.lc = S.shift;
+        S.lt = frac * A.tau * sd;
+        return;
+    }
+    if (first) {
+        S.m = u.mean;
+        S.sd = u.n > 1.0 ? sqrt(u.m2 / (u.n - 1.0)) : 0.0;
+        S.kept = u.n;
+        S.active = A.max_iter > 0;
+    } else if (u.n == S.kept || u.n < 2.0) {
+        S.active = 0;
+    } else {
+        S.kept = u.n;
+        S.m = u.mean;
+        S.sd = sqrt(u.m2 / (u.n - 1.0));
+        S.iters += 1;
+        if (S.iters >= A.max_iter) S.active = 0;
+    }
+    S.lim = A.tau * S.sd;
+    S.shift = S.m;
+}
 
 // take value v of a level (valid or not) into the thread's sums.  After the first pass the
 // shift is the level's mean, so one difference serves the test and the sums.
@@ -502,35 +555,7 @@ __global__ __launch_bounds__(kThreads, 4) void msd_kernel(const MsdArgs A) {
         // merge the pass's statistics and update every level still being refined (the decision
         // to skip a level is uniform across the work-group)
         auto update_merged = [&](int k, const Part u) {
-            if (tid == 0) {
-                Level &S = lv[k];
-                if (probe) {
-                    // centre and band of the first pass's lists: 0.9 of the limit the
-                    // pre-estimate gives, less by three standard errors of its sd
-                    const double sd = u.n > 1.0 ? sqrt(u.m2 / (u.n - 1.0)) : 0.0;
-                    const double frac = 0.9 / (1.0 + 3.0 / sqrt(fmax(2.0 * u.n, 1.0)));
-                    S.shift = u.n > 0.0 ? u.mean : S.shift;
-                    S.lc = S.shift;
-                    S.lt = frac * A.tau * sd;
-                    return;
-                }
-                if (first) {
-                    S.m = u.mean;
-                    S.sd = u.n > 1.0 ? sqrt(u.m2 / (u.n - 1.0)) : 0.0;
-                    S.kept = u.n;
-                    S.active = A.max_iter > 0;
-                } else if (u.n == S.kept || u.n < 2.0) {
-                    S.active = 0;
-                } else {
-                    S.kept = u.n;
-                    S.m = u.mean;
-                    S.sd = sqrt(u.m2 / (u.n - 1.0));
-                    S.iters += 1;
-                    if (S.iters >= A.max_iter) S.active = 0;
-                }
-                S.lim = A.tau * S.sd;
-                S.shift = S.m;
-            }
+            if (tid == 0) update_level(lv[k], u, probe, first, A);
         };
         // the listed values of level k kept by the current estimate (every one in the first
         // pass): totals of the count and of the sums of (value - centre) and its square, in a
@@ -582,25 +607,74 @@ __global__ __launch_bounds__(kThreads, 4) void msd_kernel(const MsdArgs A) {
                 S.ns2 = tot.m2 - ls.m2;
             }
         };
-        // list pass: the unlisted statistics plus the listed values the estimate keeps
-        auto list_part = [&](int k) {
-            const Part ls = list_sums(k, lv[k].lc);
-            const Level &L = lv[k];
-            Part u = {0.0, 0.0, 0.0};
-            const double cnt = L.nn + ls.n;
-            if (cnt > 0.0) {
-                const double s1 = L.ns1 + ls.mean, s2 = L.ns2 + ls.m2;
-                u.n = cnt;
-                u.mean = L.lc + s1 / cnt;
-                u.m2 = fmax(0.0, s2 - s1 * (s1 / cnt));
+        if (mode == kList) {
+            // a list pass: each wave takes levels wave, wave + 4, ... on its own (wave-only
+            // reductions, the wave's lane 0 updates the level), one barrier at the end
+            for (int k = wave; k < K; k += kWaves) {
+                const Level L = lv[k];
+                if (!L.active) continue;
+                Part u = {0.0, 0.0, 0.0};
+                if (k < klist) {
+                    // the listed values: the four waves' lists one after another
+                    const double *l = wr + list_offset(n, k);
+                    const int room = list_room(n, k);
+                    const int c0 = min(list_cnt[0][k], room), c1 = min(list_cnt[1][k], room);
+                    const int c2 = min(list_cnt[2][k], room), c3 = min(list_cnt[3][k], room);
+                    const int p1 = c0, p2 = p1 + c1, p3 = p2 + c2, c = p3 + c3;
+                    Acc a;
+                    acc_reset(a);
+                    for (int j0 = 0; j0 < c; j0 += 4 * 64) {
+                        double v[4];             // four loads in flight, then their sums in order
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int j = j0 + q * 64 + lane;
+                            const int w = (j >= p1) + (j >= p2) + (j >= p3);
+                            const int base = w == 0 ? 0 : w == 1 ? p1 : w == 2 ? p2 : p3;
+                            v[q] = j < c ? l[(int64_t)w * room + (j - base)] : 0.0;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const bool ok = j0 + q * 64 + lane < c && fabs(v[q] - L.shift) <= L.lim;
+                            const double e = ok ? v[q] - L.lc : 0.0;
+                            a.n += ok ? 1 : 0;
+                            a.s1 += e;
+                            a.s2 = fma(e, e, a.s2);
+                        }
+                    }
+                    const Part t = wave_sums(Part{(double)a.n, a.s1, a.s2});
+                    const double cnt = L.nn + t.n;
+                    if (cnt > 0.0) {
+                        const double s1 = L.ns1 + t.mean, s2 = L.ns2 + t.m2;
+                        u.n = cnt;
+                        u.mean = L.lc + s1 / cnt;
+                        u.m2 = fmax(0.0, s2 - s1 * (s1 / cnt));
+                    }
+                } else {
+                    // a level stored whole in the workspace
+                    const int64_t cnt = (int64_t)(n >> k);
+                    const double *vals = wr + arr_offset(n, k);
+                    Acc a;
+                    acc_reset(a);
+                    for (int64_t i0 = 0; i0 < cnt; i0 += 4 * 64) {
+                        double v[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int64_t i = i0 + q * 64 + lane;
+                            v[q] = i < cnt ? vals[i] : 0.0;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) take(a, L, false, i0 + q * 64 + lane < cnt, v[q]);
+                    }
+                    u = wave_merge(acc_part(a, L.shift));
+                }
+                if (lane == 0) update_level(lv[k], u, false, false, A);
             }
-            return u;
-        };
+            __syncthreads();
+            continue;
+        }
         for (int k = 0; k < klist; ++k) {
             if (!(first || lv[k].active)) continue;
-            if (mode == kList) {
-                update_merged(k, list_part(k));
-            } else if (k < 3) {
+            if (k < 3) {
                 const Acc &a = k == 0 ? a0 : k == 1 ? a1 : a2;
                 const uint32_t nw = k == 0 ? n0w : k == 1 ? n1w : n2w;
                 Part tot;
