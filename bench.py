@@ -83,9 +83,9 @@ def launch_bytes(info, i: int, n_dm: int, planes: bool = True) -> int:
 FAMILY = {"ig1": 1, "ig2": 2, "ig3": 3, "bd8": 4, "bd16": 5, "bd32": 6, "dit": 7}
 
 
-def launch_kernel_name(method: str, info, i: int) -> str:
+def launch_kernel_name(method: str, info, i: int, planes: bool = True) -> str:
     """Kernel symbol of filter launch i, as rocprofv3 lists it (the work-group size is the one the
-    library's planner reports for the launch)."""
+    library's planner reports for the launch; planes: the launch stores the planes)."""
     if method == "exh":
         if info.launch_first_level[i] < 0:
             return "spd::scales_kernel"
@@ -93,13 +93,15 @@ def launch_kernel_name(method: str, info, i: int) -> str:
         group = 16 if int(info.max_width) <= 4096 else 64          # widths per max-only group
         return f"spd::exh_kernel<true, {multi}, {group}>"
     first = "true" if info.launch_first_level[i] == 0 else "false"
-    return f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}, false, {int(info.launch_threads[i])}>"
+    return (f"spd::step_kernel<{first}, {FAMILY.get(method, 0)}, false, {int(info.launch_threads[i])}, "
+            f"{'true' if planes else 'false'}>")
 
 
 def launch_valu_ops(method: str, cfg, info, i: int, n_dm: int, n_in: int) -> float:
     """Algorithmic FP32 lane operations of filter launch i.  Lossy levels: per slot one add per
-    unit of the widest boxcar (running sums) plus multiply, max and width select per width;
-    the exhaustive set: add, multiply and max per (start, width) pair that fits."""
+    unit of the widest boxcar (running sums) plus multiply, max and width select per width (a
+    candidates-only search needs no width per slot: multiply and max); the exhaustive set: add,
+    multiply and max per (start, width) pair that fits."""
     f, c = int(info.launch_first_level[i]), int(info.launch_levels[i])
     if f < 0:
         return 0.0
@@ -114,7 +116,7 @@ def launch_valu_ops(method: str, cfg, info, i: int, n_dm: int, n_in: int) -> flo
     for k in range(f, f + c):
         ws, sh = lw[k], int(info.level_shift[k])
         umax = (ws[-1] - ws[0]) // (1 << sh) + 1
-        ops += n_dm * int(info.plane_slots[k]) * (umax + 3 * len(ws))
+        ops += n_dm * int(info.plane_slots[k]) * (umax + (3 if cfg.planes else 2) * len(ws))
     return ops
 
 
@@ -136,7 +138,7 @@ def dominant_entry(method: str, cfg, run, w, reps: int, lms=None) -> dict:
     gbs = launch_bytes(info, dom, w.n_dm, planes=cfg.planes) / sec / 1e9
     tops = launch_valu_ops(method, cfg, info, dom, w.n_dm, w.n) / sec / 1e12
     hf, vf = gbs / HBM_PEAK_GBS, tops / VALU_PEAK_TOPS
-    return {"kernel": launch_kernel_name(method, info, dom), "ms": round(lms[dom], 4),
+    return {"kernel": launch_kernel_name(method, info, dom, planes=cfg.planes), "ms": round(lms[dom], 4),
             "launch_ms": [round(v, 4) for v in lms], "gbs": round(gbs, 1),
             "hbm_frac": round(hf, 4), "valu_tops": round(tops, 2), "valu_frac": round(vf, 4),
             "valu_frac_vs_157": round(tops / VALU_PEAK_TOPS_ALT, 4),
@@ -301,7 +303,7 @@ def main():
         y.copy_(x)                                          # device-to-device copy
         torch.cuda.synchronize()
         strided_bytes = x[:, 64:].numel() * 4
-        launches = [{"kernel": launch_kernel_name(args.method, info, i),
+        launches = [{"kernel": launch_kernel_name(args.method, info, i, planes=cfg.planes),
                      "algorithmic_bytes": launch_bytes(info, i, w.n_dm, planes=cfg.planes)}
                     for i in range(info.n_launches)]
         print(json.dumps({"probe": "ok", "method": args.method, "search_launches": 4,

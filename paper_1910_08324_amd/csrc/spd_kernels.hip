@@ -128,8 +128,9 @@ template <> struct Fam<7> { static constexpr int U1 = 1, U2 = 1, WAVES = 8;
 
 // All widths of the group fit: straight-line evaluation of a compiled-in width pattern.
 // X enters holding the carried prefixes and leaves holding the sum over UMAX units.
-// bu receives the unit count of the best width (0 if none).
-template <int UMAX, uint64_t MASK>
+// W: bu receives the unit count of the best width (0 if none); without W only the maximum is
+// kept (the same value: the largest of the same products).
+template <int UMAX, uint64_t MASK, bool W>
 __device__ __forceinline__ void bank_fixed(const float *y, const float *rt, float X[kGroup],
                                            float best[kGroup], int bu[kGroup]) {
     constexpr int NW = (kGroup + UMAX - 1 + 3) / 4;
@@ -151,16 +152,21 @@ __device__ __forceinline__ void bank_fixed(const float *y, const float *rt, floa
 #pragma unroll
             for (int q = 0; q < kGroup; ++q) {
                 const float v = X[q] * r;
-                const bool gt = v > best[q];
-                best[q] = gt ? v : best[q];
-                bu[q] = gt ? (u + 1) : bu[q];
+                if (W) {
+                    const bool gt = v > best[q];
+                    best[q] = gt ? v : best[q];
+                    bu[q] = gt ? (u + 1) : bu[q];
+                } else {
+                    best[q] = fmaxf(best[q], v);
+                }
             }
         }
     }
 }
 
 // Any width set, with the valid-only check per slot.  Xc receives the sum over `ufull` units
-// (the carry handed to the next BoxDIT level).
+// (the carry handed to the next BoxDIT level).  W as for bank_fixed.
+template <bool W>
 __device__ __forceinline__ void bank_generic(const float *y, const float *rt, int umax,
                                              uint64_t emask, int ufull, int k, int base,
                                              const int64_t room[kGroup], float X[kGroup],
@@ -183,9 +189,13 @@ __device__ __forceinline__ void bank_generic(const float *y, const float *rt, in
                 for (int q = 0; q < kGroup; ++q) {
                     float v = X[q] * r;
                     if (Lw > room[q]) v = SPD_NEG_INF;
-                    const bool gt = v > best[q];
-                    best[q] = gt ? v : best[q];
-                    bu[q] = gt ? (u + 1) : bu[q];
+                    if (W) {
+                        const bool gt = v > best[q];
+                        best[q] = gt ? v : best[q];
+                        bu[q] = gt ? (u + 1) : bu[q];
+                    } else {
+                        best[q] = fmaxf(best[q], v);
+                    }
                 }
             }
             if (u + 1 == ufull) {
@@ -301,8 +311,10 @@ __device__ __forceinline__ void write_rec(const StepArgs &A, const G &V, RecStep
 }
 
 // One tile (DM row d, tile `tile`) of a cascade launch.  A holds what every beam of the launch
-// shares (levels, width patterns, tile length); G the beam's buffers and sizes.
-template <bool FIRST, int FAM, bool RHO, int NTH, class G>
+// shares (levels, width patterns, tile length); G the beam's buffers and sizes.  W: the planes
+// are stored (A.write_planes), so the banks also track the best width; candidates-only
+// launches keep the maxima only.
+template <bool FIRST, int FAM, bool RHO, int NTH, bool W, class G>
 __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const int d,
                                           const int tile, float *lds, uint32_t *st_cnt) {
     const int tid = threadIdx.x;
@@ -454,18 +466,18 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
                 for (int q = 0; q < kGroup; ++q) X[q] = has_carry ? cj[m0 + q] : 0.0f;
                 const bool fast = ((int64_t)(ma + kGroup - 1) << k) <= fast_lim;
                 if (FAM != 0 && fast && pat == 1) {
-                    bank_fixed<Fam<FAM>::U1, Fam<FAM>::M1>(yj + m0, rt, X, best, bu);
+                    bank_fixed<Fam<FAM>::U1, Fam<FAM>::M1, W>(yj + m0, rt, X, best, bu);
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q) Xc[q] = X[q];
                 } else if (FAM != 0 && fast && pat == 2) {
-                    bank_fixed<Fam<FAM>::U2, Fam<FAM>::M2>(yj + m0, rt, X, best, bu);
+                    bank_fixed<Fam<FAM>::U2, Fam<FAM>::M2, W>(yj + m0, rt, X, best, bu);
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q) Xc[q] = X[q];
                 } else {
                     int64_t room[kGroup];
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q) room[q] = (int64_t)V.n_in() - ((int64_t)(ma + q) << k);
-                    bank_generic(yj + m0, rt, umax, L.evalmask, L.ufull, k, base, room, X, Xc, best, bu);
+                    bank_generic<W>(yj + m0, rt, umax, L.evalmask, L.ufull, k, base, room, X, Xc, best, bu);
                 }
                 if (cg) {
                     // the last level's longest boxcar is the next step's carried prefix
@@ -475,7 +487,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
                 int bw[kGroup];
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) bw[q] = bu[q] ? base + (bu[q] << k) : 0;
-                if (!A.write_planes) {
+                if (!W) {
                     // candidates only: nothing stored; the peak finder forms what it reads again
                 } else if (ma + kGroup <= V.slots(j)) {
                     *reinterpret_cast<float4 *>(rowY + ma) = make_float4(best[0], best[1], best[2], best[3]);
@@ -578,20 +590,20 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
 
 
 // One launch for one beam: work-group = (DM row, tile) of NTH threads.
-template <bool FIRST, int FAM, bool RHO, int NTH>
+template <bool FIRST, int FAM, bool RHO, int NTH, bool W>
 __global__ __launch_bounds__(NTH, Fam<FAM>::WAVES) void step_kernel(const StepArgs A) {
     extern __shared__ float lds[];
     __shared__ uint32_t st_cnt[kStepMaxLevels];
     const int d = blockIdx.x / A.n_tiles;
     const int tile = blockIdx.x - d * A.n_tiles;
     if (d >= A.n_dm) return;
-    step_tile<FIRST, FAM, RHO, NTH>(A, ArgGeom{A}, d, tile, lds, st_cnt);
+    step_tile<FIRST, FAM, RHO, NTH, W>(A, ArgGeom{A}, d, tile, lds, st_cnt);
 }
 
 // One launch for many beams (same levels and tile length, any sizes): a persistent grid walks
 // the work items (beam, DM row, tile) in order; item i belongs to the beam b with
 // item_base[b] <= i < item_base[b + 1].
-template <bool FIRST, int FAM>
+template <bool FIRST, int FAM, bool W>
 __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel_batch(const StepBatchArgs B) {
     extern __shared__ float lds[];
     __shared__ uint32_t st_cnt[kStepMaxLevels];
@@ -605,7 +617,7 @@ __global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel_bat
         const int d = (int)(local / V.n_tiles());
         const int tile = (int)(local - (int64_t)d * V.n_tiles());
         if (item != (int64_t)blockIdx.x) lds_barrier();   // the previous item is done with LDS
-        step_tile<FIRST, FAM, false, kStepThreads>(B.s, V, d, tile, lds, st_cnt);
+        step_tile<FIRST, FAM, false, kStepThreads, W>(B.s, V, d, tile, lds, st_cnt);
     }
 }
 
@@ -1428,10 +1440,14 @@ int launch_evalmask(const MaskArgs &a, void *stream) {
 template <bool FIRST, int FAM, int NTH>
 static void launch_nth(const StepArgs &a, int lds_bytes, hipStream_t st) {
     const dim3 grid((unsigned)((int64_t)a.n_dm * a.n_tiles));
-    if (a.rho)
-        hipLaunchKernelGGL((step_kernel<FIRST, FAM, true, NTH>), grid, dim3(NTH), lds_bytes, st, a);
+    if (a.rho && a.write_planes)
+        hipLaunchKernelGGL((step_kernel<FIRST, FAM, true, NTH, true>), grid, dim3(NTH), lds_bytes, st, a);
+    else if (a.rho)
+        hipLaunchKernelGGL((step_kernel<FIRST, FAM, true, NTH, false>), grid, dim3(NTH), lds_bytes, st, a);
+    else if (a.write_planes)
+        hipLaunchKernelGGL((step_kernel<FIRST, FAM, false, NTH, true>), grid, dim3(NTH), lds_bytes, st, a);
     else
-        hipLaunchKernelGGL((step_kernel<FIRST, FAM, false, NTH>), grid, dim3(NTH), lds_bytes, st, a);
+        hipLaunchKernelGGL((step_kernel<FIRST, FAM, false, NTH, false>), grid, dim3(NTH), lds_bytes, st, a);
 }
 
 // The work-group size is the planner's (StepArgs::nth): 128 threads only for IG(1).
@@ -1464,8 +1480,12 @@ static int launch_step_fam(const StepArgs &a, int fam, int lds_bytes, hipStream_
 
 template <bool FIRST, int FAM>
 static int launch_batch(const StepBatchArgs &a, int lds_bytes, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((step_kernel_batch<FIRST, FAM>), dim3((unsigned)grid), dim3(kStepThreads),
-                       lds_bytes, st, a);
+    if (a.s.write_planes)
+        hipLaunchKernelGGL((step_kernel_batch<FIRST, FAM, true>), dim3((unsigned)grid),
+                           dim3(kStepThreads), lds_bytes, st, a);
+    else
+        hipLaunchKernelGGL((step_kernel_batch<FIRST, FAM, false>), dim3((unsigned)grid),
+                           dim3(kStepThreads), lds_bytes, st, a);
     return (int)hipGetLastError();
 }
 

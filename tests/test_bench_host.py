@@ -24,11 +24,11 @@ def info(segment, first_levels, threads):
 
 def test_kernel_names_follow_planned_work_group_size(bench):
     assert bench.launch_kernel_name("ig1", info(3072, [0, 5], [128, 128]), 0) == \
-        "spd::step_kernel<true, 1, false, 128>"
+        "spd::step_kernel<true, 1, false, 128, true>"
     assert bench.launch_kernel_name("ig1", info(4096, [0, 4], [256, 256]), 1) == \
-        "spd::step_kernel<false, 1, false, 256>"
-    assert bench.launch_kernel_name("bd16", info(3072, [0, 5], [256, 256]), 1) == \
-        "spd::step_kernel<false, 5, false, 256>"
+        "spd::step_kernel<false, 1, false, 256, true>"
+    assert bench.launch_kernel_name("bd16", info(3072, [0, 5], [256, 256]), 1, planes=False) == \
+        "spd::step_kernel<false, 5, false, 256, false>"
 
 
 def test_planner_reports_work_group_size():
@@ -51,7 +51,8 @@ def test_planner_reports_work_group_size():
 
 def test_read_traffic_by_shape(bench, tmp_path, monkeypatch):
     f = tmp_path / "counters.txt"
-    k128, k256 = "spd::step_kernel<true, 1, false, 128>", "spd::step_kernel<true, 1, false, 256>"
+    k128, k256 = ("spd::step_kernel<true, 1, false, 128, true>",
+                  "spd::step_kernel<true, 1, false, 256, true>")
     f.write_text("\n".join([
         "# comment: ignored", "kernel | a | b", "method: ig1", f"kernel: {k128}", "segment: 3072",
         "step_levels: 4", "kernel_source_sha256_16: abc", "hbm_bytes_per_launch: 1.5e10",
