@@ -126,15 +126,23 @@ template <> struct Fam<6> { static constexpr int U1 = 32, U2 = 32, WAVES = 8;
 template <> struct Fam<7> { static constexpr int U1 = 1, U2 = 1, WAVES = 8;
                             static constexpr uint64_t M1 = 1, M2 = 1; };
 
+// Where a group's LDS window is read ahead (before the previous batch's barrier): the sets
+// whose launches wait on those reads and gain more than the lower occupancy costs them (the
+// window stays in registers across the barrier: 5 waves per SIMD instead of 7-8).  Measured
+// on the 4096 x 262144 beam: IG(3) 8.59 -> 8.10 ms (planes) and 8.45 -> 7.68 ms (candidates
+// only), BD-32 candidates only 9.29 -> 8.78 ms; BD-32 with planes, BD-16 and IG(2) were slower.
+template <int FAM, bool W> struct StepShape {
+    static constexpr bool PREFETCH = FAM == 3 || (FAM == 6 && !W);
+    static constexpr int WAVES = PREFETCH ? 5 : Fam<FAM>::WAVES;
+};
+
+
 // All widths of the group fit: straight-line evaluation of a compiled-in width pattern.
 // X enters holding the carried prefixes and leaves holding the sum over UMAX units.
 // W: bu receives the unit count of the best width (0 if none); without W only the maximum is
 // kept (the same value: the largest of the same products).
-template <int UMAX, uint64_t MASK, bool W>
-__device__ __forceinline__ void bank_fixed(const float *y, const float *rt, float X[kGroup],
-                                           float best[kGroup], int bu[kGroup]) {
-    constexpr int NW = (kGroup + UMAX - 1 + 3) / 4;
-    float w[4 * NW];
+template <int NW>
+__device__ __forceinline__ void window_load(const float *y, float w[4 * NW]) {
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
         const float4 v = *reinterpret_cast<const float4 *>(y + 4 * q);
@@ -143,6 +151,12 @@ __device__ __forceinline__ void bank_fixed(const float *y, const float *rt, floa
         w[4 * q + 2] = v.z;
         w[4 * q + 3] = v.w;
     }
+}
+
+// the same on a window already in registers (w: units m0 .. m0 + 4 NW - 1 of the level)
+template <int UMAX, uint64_t MASK, bool W>
+__device__ __forceinline__ void bank_fixed_win(const float *w, const float *rt, float X[kGroup],
+                                               float best[kGroup], int bu[kGroup]) {
 #pragma unroll
     for (int u = 0; u < UMAX; ++u) {
 #pragma unroll
@@ -162,6 +176,15 @@ __device__ __forceinline__ void bank_fixed(const float *y, const float *rt, floa
             }
         }
     }
+}
+
+template <int UMAX, uint64_t MASK, bool W>
+__device__ __forceinline__ void bank_fixed(const float *y, const float *rt, float X[kGroup],
+                                           float best[kGroup], int bu[kGroup]) {
+    constexpr int NW = (kGroup + UMAX - 1 + 3) / 4;
+    float w[4 * NW];
+    window_load<NW>(y, w);
+    bank_fixed_win<UMAX, MASK, W>(w, rt, X, best, bu);
 }
 
 // Any width set, with the valid-only check per slot.  Xc receives the sum over `ufull` units
@@ -439,6 +462,13 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         uint16_t *rowW = V.W() + V.plane_off(j) + (int64_t)d * V.pitch(j);
         // a group is "fast" when the widest boxcar of its last slot ends inside the data
         const int64_t fast_lim = (int64_t)V.n_in() - base - ((int64_t)umax << k);
+        // some dense width sets: a group's window is read from LDS before the previous batch's
+        // barrier (it lies above every unit that batch writes), so its latency overlaps the
+        // previous batch's stores and barrier
+        constexpr bool kPre = StepShape<FAM, W>::PREFETCH;
+        constexpr int kWin4 = kPre ? (kGroup + Fam<FAM>::U1 - 1 + 3) / 4 : 1;
+        float win[4 * kWin4];
+        if (kPre && tid < ngroups) window_load<kWin4>(yj + tid * kGroup, win);
         for (int gb = 0; gb < ngroups; gb += NTH) {
             const int g = gb + tid;
             const int m0 = g * kGroup;
@@ -455,9 +485,14 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
             const int n0 = (m0 - cs1) >> 1;
             float nu0 = 0.0f, nu1 = 0.0f;
             if (form_next && g < ngroups) {
-                const float4 w0 = *reinterpret_cast<const float4 *>(yj + m0);
-                nu0 = w0.x + w0.y;
-                nu1 = w0.z + w0.w;
+                if (kPre) {
+                    nu0 = win[0] + win[1];
+                    nu1 = win[2] + win[3];
+                } else {
+                    const float4 w0 = *reinterpret_cast<const float4 *>(yj + m0);
+                    nu0 = w0.x + w0.y;
+                    nu1 = w0.z + w0.w;
+                }
             }
             float Xc[kGroup];
             if (act) {
@@ -466,11 +501,17 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
                 for (int q = 0; q < kGroup; ++q) X[q] = has_carry ? cj[m0 + q] : 0.0f;
                 const bool fast = ((int64_t)(ma + kGroup - 1) << k) <= fast_lim;
                 if (FAM != 0 && fast && pat == 1) {
-                    bank_fixed<Fam<FAM>::U1, Fam<FAM>::M1, W>(yj + m0, rt, X, best, bu);
+                    if (kPre)
+                        bank_fixed_win<Fam<FAM>::U1, Fam<FAM>::M1, W>(win, rt, X, best, bu);
+                    else
+                        bank_fixed<Fam<FAM>::U1, Fam<FAM>::M1, W>(yj + m0, rt, X, best, bu);
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q) Xc[q] = X[q];
                 } else if (FAM != 0 && fast && pat == 2) {
-                    bank_fixed<Fam<FAM>::U2, Fam<FAM>::M2, W>(yj + m0, rt, X, best, bu);
+                    if (kPre)
+                        bank_fixed_win<Fam<FAM>::U2, Fam<FAM>::M2, W>(win, rt, X, best, bu);
+                    else
+                        bank_fixed<Fam<FAM>::U2, Fam<FAM>::M2, W>(yj + m0, rt, X, best, bu);
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q) Xc[q] = X[q];
                 } else {
@@ -503,6 +544,8 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
                         }
                 }
             }
+            // the window of this thread's group in the next batch
+            if (kPre && g + NTH < ngroups) window_load<kWin4>(yj + (g + NTH) * kGroup, win);
             if (A.want_cand) {
                 const float gmax = fmaxf(fmaxf(best[0], best[1]), fmaxf(best[2], best[3]));
                 if (__ballot(gmax > A.threshold)) {
@@ -591,7 +634,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
 
 // One launch for one beam: work-group = (DM row, tile) of NTH threads.
 template <bool FIRST, int FAM, bool RHO, int NTH, bool W>
-__global__ __launch_bounds__(NTH, Fam<FAM>::WAVES) void step_kernel(const StepArgs A) {
+__global__ __launch_bounds__(NTH, (StepShape<FAM, W>::WAVES)) void step_kernel(const StepArgs A) {
     extern __shared__ float lds[];
     __shared__ uint32_t st_cnt[kStepMaxLevels];
     const int d = blockIdx.x / A.n_tiles;
@@ -604,7 +647,7 @@ __global__ __launch_bounds__(NTH, Fam<FAM>::WAVES) void step_kernel(const StepAr
 // the work items (beam, DM row, tile) in order; item i belongs to the beam b with
 // item_base[b] <= i < item_base[b + 1].
 template <bool FIRST, int FAM, bool W>
-__global__ __launch_bounds__(kStepThreads, Fam<FAM>::WAVES) void step_kernel_batch(const StepBatchArgs B) {
+__global__ __launch_bounds__(kStepThreads, (StepShape<FAM, W>::WAVES)) void step_kernel_batch(const StepBatchArgs B) {
     extern __shared__ float lds[];
     __shared__ uint32_t st_cnt[kStepMaxLevels];
     const ConstBeamPtr beams = (ConstBeamPtr)B.beams;
