@@ -128,12 +128,14 @@ template <> struct Fam<7> { static constexpr int U1 = 1, U2 = 1, WAVES = 8;
 
 // Where a group's LDS window is read ahead (before the previous batch's barrier): the sets
 // whose launches wait on those reads and gain more than the lower occupancy costs them (the
-// window stays in registers across the barrier: 5 waves per SIMD instead of 7-8).  Measured
-// on the 4096 x 262144 beam: IG(3) 8.59 -> 8.10 ms (planes) and 8.45 -> 7.68 ms (candidates
-// only), BD-32 candidates only 9.29 -> 8.78 ms; BD-32 with planes, BD-16 and IG(2) were slower.
+// window stays in registers across the barrier: 5 waves per SIMD instead of 7-8 for the dense
+// sets; IG(1)'s three float4 fit the 8-wave budget).  Measured on the 4096 x 262144 beam: IG(3)
+// 8.59 -> 8.10 ms (planes) and 8.45 -> 7.68 ms (candidates only), BD-32 candidates only
+// 9.29 -> 8.78 ms, IG(1) candidates only 3.29 -> 3.22 ms; BD-32 and IG(1) with planes, BD-16
+// and IG(2) were slower.
 template <int FAM, bool W> struct StepShape {
-    static constexpr bool PREFETCH = FAM == 3 || (FAM == 6 && !W);
-    static constexpr int WAVES = PREFETCH ? 5 : Fam<FAM>::WAVES;
+    static constexpr bool PREFETCH = FAM == 3 || ((FAM == 1 || FAM == 6) && !W);
+    static constexpr int WAVES = (PREFETCH && FAM != 1) ? 5 : Fam<FAM>::WAVES;
 };
 
 
