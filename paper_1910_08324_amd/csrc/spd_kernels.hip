@@ -126,16 +126,17 @@ template <> struct Fam<6> { static constexpr int U1 = 32, U2 = 32, WAVES = 8;
 template <> struct Fam<7> { static constexpr int U1 = 1, U2 = 1, WAVES = 8;
                             static constexpr uint64_t M1 = 1, M2 = 1; };
 
-// Where a group's LDS window is read ahead (before the previous batch's barrier): the sets
-// whose launches wait on those reads and gain more than the lower occupancy costs them (the
-// window stays in registers across the barrier: 5 waves per SIMD instead of 7-8 for the dense
-// sets; IG(1)'s three float4 fit the 8-wave budget).  Measured on the 4096 x 262144 beam: IG(3)
-// 8.59 -> 8.10 ms (planes) and 8.45 -> 7.68 ms (candidates only), BD-32 candidates only
-// 9.29 -> 8.78 ms, IG(1) candidates only 3.29 -> 3.22 ms; BD-32 and IG(1) with planes, BD-16
-// and IG(2) were slower.
+// Where a group's LDS window is read ahead (before the previous batch's barrier): the launches
+// that wait on those reads and gain more than the lower occupancy costs them (the window stays
+// in registers across the barrier: waves per SIMD as the registers allow without spilling).
+// Measured on the 4096 x 262144 beam, planes / candidates only: IG(3) 8.59 -> 8.10 / 8.45 ->
+// 7.68 ms, BD-8 4.73 -> 4.58 / 4.48 -> 3.86 ms, BD-16 - / 6.24 -> 5.85 ms, BD-32 - / 9.29 ->
+// 8.78 ms, IG(1) - / 3.29 -> 3.22 ms; IG(2) both ways, and BD-16, BD-32 and IG(1) with planes,
+// were slower or no faster.
 template <int FAM, bool W> struct StepShape {
-    static constexpr bool PREFETCH = FAM == 3 || ((FAM == 1 || FAM == 6) && !W);
-    static constexpr int WAVES = (PREFETCH && FAM != 1) ? 5 : Fam<FAM>::WAVES;
+    static constexpr bool PREFETCH = FAM == 3 || FAM == 4 || ((FAM == 1 || FAM == 5 || FAM == 6) && !W);
+    static constexpr int WAVES = !PREFETCH ? Fam<FAM>::WAVES
+                               : FAM == 1 ? 8 : FAM == 4 ? 7 : FAM == 5 ? 6 : 5;
 };
 
 
