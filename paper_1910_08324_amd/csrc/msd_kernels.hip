@@ -269,16 +269,18 @@ __device__ __forceinline__ void level_step(double &v, double *slots, int lane, i
         slots[kSlotK + (lane >> (K - 2))] = (FULL || s + (1 << K) <= n) ? v : __builtin_nan("");
 }
 
-// lanes below this one
-__device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
+// how many of the lanes below this one have their bit set in b (mbcnt)
+__device__ __forceinline__ int count_below(uint64_t b) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+}
 
 // append the values of the lanes whose `far` is set to the wave's list, in lane order after the
 // values appended before (a full list still counts them, which marks the overflow)
-__device__ __forceinline__ void list_append(bool far, double v, double *list, int &cnt, int room,
-                                            int lane) {
+__device__ __forceinline__ void list_append(bool far, double v, double *list, int &cnt, int room) {
     const uint64_t b = __ballot(far);
     if (b) {
-        const int i = cnt + __popcll(b & lanes_below(lane));
+        const int i = cnt + count_below(b);
         if (far && i < room) list[i] = v;
         cnt += __popcll(b);
     }
@@ -289,15 +291,14 @@ __device__ __forceinline__ void list_append(bool far, double v, double *list, in
 // the list threshold also go to the wave's list of the level.
 template <bool LIST>
 __device__ __forceinline__ void take_w(Acc &a, uint32_t &nw, const Level &L, bool first,
-                                       bool valid, double v, double *list, int &cnt, int room,
-                                       int lane) {
+                                       bool valid, double v, double *list, int &cnt, int room) {
     const double d = v - L.shift;
     const bool ok = valid && (first || fabs(d) <= L.lim);
     const double e = ok ? d : 0.0;           // (d may be NaN for a value past the data)
     nw += (uint32_t)__popcll(__ballot(ok));
     a.s1 += e;
     a.s2 = fma(e, e, a.s2);
-    if (LIST) list_append(valid && !(fabs(d) <= L.lt), v, list, cnt, room, lane);   // lc == shift
+    if (LIST) list_append(valid && !(fabs(d) <= L.lt), v, list, cnt, room);   // lc == shift
 }
 
 // statistics of a level all of whose values share one shift: the work-group's totals of the
@@ -446,19 +447,19 @@ __global__ __launch_bounds__(kThreads, 4) void msd_kernel(const MsdArgs A) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     take_w<LIST>(a0, n0w, L0, first, FULL || s + q < n, v0[q], list_of(0), lc_[0],
-                                 list_room(n, 0), lane);
+                                 list_room(n, 0));
             // levels 1, 2 within the thread
             const double v1a = v0[0] + v0[1], v1b = v0[2] + v0[3];
             if (on1) {
                 take_w<LIST>(a1, n1w, L1, first, FULL || s + 2 <= n, v1a, list_of(1), lc_[1],
-                             list_room(n, 1), lane);
+                             list_room(n, 1));
                 take_w<LIST>(a1, n1w, L1, first, FULL || s + 4 <= n, v1b, list_of(1), lc_[1],
-                             list_room(n, 1), lane);
+                             list_room(n, 1));
             }
             double v = v1a + v1b;
             if (on2)
                 take_w<LIST>(a2, n2w, L2, first, FULL || s + 4 <= n, v, list_of(2), lc_[2],
-                             list_room(n, 2), lane);
+                             list_room(n, 2));
             // levels 3..8 across lanes: after step k, lane l holds the value of level k that starts
             // at its own samples when l is a multiple of 2^(k-2); holders park their values in the
             // wave's 64 slots (level k from slot 64 - 2^(9-k), one per holder, NaN past the data), and
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(kThreads, 4) void msd_kernel(const MsdArgs A) {
                                                                     : 0xffull << 48;
                         const uint64_t bk = b & run;
                         if (bk) {
-                            const int i = lc_[k] + __popcll(bk & lanes_below(lane));
+                            const int i = lc_[k] + count_below(bk);
                             if (far && my_k == k && i < list_room(n, k)) list_of(k)[i] = mv;
                             lc_[k] += __popcll(bk);
                         }
