@@ -2,28 +2,29 @@
 // deviation with iterative outlier rejection, for the samples and for every power-of-two
 // decimation of them.  One work-group per row, FP64 throughout.
 //
-// A pass reads the row once and serves every level at the same time.  The row streams through
-// in tiles of 1024 samples, one float4 per thread; inside a tile the decimated values of levels
-// 1..8 are formed in registers (levels 1, 2 within a thread, 3..8 by pairwise sums across lanes,
-// moved by DPP row shifts and readlane rather than through LDS)
-// and each lane accumulates the values it holds.  Values of levels 9 and up (at most 1/256 of the
-// samples) are formed once, in the first pass, into the workspace, and later passes read them
-// from there.  Per level, each thread keeps a count and the sums of (value - shift) and of its
-// square, with the shift the level's current mean estimate; after the pass the threads' partial
-// statistics (count, mean, sum of squared deviations) are merged pairwise with Chan, Golub &
-// LeVeque's formula in a fixed order.  Levels 0..2, which every lane serves, count their kept
-// values per wave instead, and their lanes' sums around the common shift are totalled directly.
-// Levels converge independently; the row's passes stop when every level has.
+// A read of the row serves every level at once.  The row streams through in tiles of 1024
+// samples, one float4 per thread; inside a tile the decimated values of levels 1..8 are formed
+// in registers (levels 1, 2 within a thread, 3..8 by pairwise sums across lanes, moved by DPP
+// row shifts and readlane rather than through LDS).  Levels 0..5 are accumulated as they stream
+// by: per level, each thread keeps a count and the sums of (value - shift) and of its square,
+// the shift being the level's current mean estimate; levels 0..2, which every lane serves, count
+// their kept values per wave and total their lanes' sums directly, levels 3..5 merge per-lane
+// partials (count, mean, sum of squared deviations) with Chan, Golub & LeVeque's formula in a
+// fixed order.  Levels 6 and up (at most 1/32 of the values) are stored whole in the workspace by
+// the first read and taken from there in every pass.  Levels converge independently; the row's
+// passes stop when every level has.
 //
-// Later passes need not read the row.  A "build" pass (a full read with rejection) also lists,
-// per level, every value farther than 0.9 of the current limit from the current mean, and keeps
-// the count and sums of the values it did not list.  While the limit of a later pass still
-// covers the whole unlisted band (|value - list centre| <= list threshold implies
-// |value - mean| <= limit, checked with a margin for rounding), every unlisted value is kept, so
-// the pass needs only the listed values: it tests them exactly as a full read would and adds
-// the unlisted statistics.  The kept sets, hence the counts, pass counts and stopping decisions,
-// are those of full reads; only the order of the FP64 sums differs.  When the band is no longer
-// covered, or a list overflowed its room, the next pass is a build pass again.
+// Most passes need not read the row.  Before the first read a pre-estimate (mean and sd of 8
+// tiles spread over the row) centres a band for each level 0..5; the first read (the estimate
+// that keeps every value) lists, per level and wave, every value outside the band and keeps the
+// count and sums of the values it did not list.  While the limit of a later pass still covers
+// the whole band (|value - list centre| <= band half-width implies |value - mean| <= limit,
+// checked with a margin for rounding), every unlisted value is kept, so the pass needs only the
+// listed values: it tests them exactly as a full read would and adds the unlisted statistics;
+// such a pass runs its levels side by side, one wave per level.  The kept sets, hence the counts,
+// pass counts and stopping decisions, are those of full reads; only the order of the FP64 sums
+// differs (and is fixed).  When the band is no longer covered, or a list overflowed its room, the
+// pass reads the row again and lists anew around its own estimate (0.8 of its limit).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
