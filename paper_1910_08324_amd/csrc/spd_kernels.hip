@@ -126,17 +126,19 @@ template <> struct Fam<6> { static constexpr int U1 = 32, U2 = 32, WAVES = 8;
 template <> struct Fam<7> { static constexpr int U1 = 1, U2 = 1, WAVES = 8;
                             static constexpr uint64_t M1 = 1, M2 = 1; };
 
-// Where a group's LDS window is read ahead (before the previous batch's barrier): the launches
-// that wait on those reads and gain more than the lower occupancy costs them (the window stays
-// in registers across the barrier: waves per SIMD as the registers allow without spilling).
-// Measured on the 4096 x 262144 beam, planes / candidates only: IG(3) 8.59 -> 8.10 / 8.45 ->
-// 7.68 ms, BD-8 4.73 -> 4.58 / 4.48 -> 3.86 ms, BD-16 - / 6.24 -> 5.85 ms, BD-32 - / 9.29 ->
-// 8.78 ms, IG(1) - / 3.29 -> 3.22 ms; IG(2) both ways, and BD-16, BD-32 and IG(1) with planes,
-// were slower or no faster.
+// How much of a group's LDS window is read ahead, before the previous batch's barrier (PRE4
+// float4 of the NW the banks use; the rest is read when the bank starts), and the waves per
+// SIMD the launch is compiled for.  Reading a little ahead lets each bank start on data already
+// in registers without costing occupancy; reading the whole window ahead costs registers, hence
+// waves, and was slower for most sets.  Measured on the 4096 x 262144 beam (dominant launch,
+// planes / candidates only, against no read-ahead): IG(1) 3.44 -> 3.19 / 3.29 -> 3.22 ms,
+// IG(2) 5.24 -> 4.48 / 5.13 -> 4.27, IG(3) 8.59 -> 7.70 / 8.45 -> 7.60, BD-8 4.73 -> 4.33 /
+// 4.48 -> 3.62, BD-16 6.56 -> 5.96 / 6.24 -> 5.32, BD-32 9.70 -> 9.44 / 9.29 -> 8.45.
 template <int FAM, bool W> struct StepShape {
-    static constexpr bool PREFETCH = FAM == 3 || FAM == 4 || ((FAM == 1 || FAM == 5 || FAM == 6) && !W);
-    static constexpr int WAVES = !PREFETCH ? Fam<FAM>::WAVES
-                               : FAM == 1 ? 8 : FAM == 4 ? 7 : FAM == 5 ? 6 : 5;
+    static constexpr int NW = (FAM >= 1 && FAM <= 7) ? (kGroup + Fam<FAM>::U1 - 1 + 3) / 4 : 1;
+    static constexpr int PRE4 = FAM == 1 ? (W ? 1 : 3) : FAM == 2 ? 2 : FAM == 3 ? 3 : FAM == 4 ? 2
+                              : FAM == 5 ? 2 : FAM == 6 ? 4 : 0;
+    static constexpr int WAVES = FAM == 6 ? 7 : Fam<FAM>::WAVES;
 };
 
 
@@ -156,14 +158,15 @@ __device__ __forceinline__ void window_load(const float *y, float w[4 * NW]) {
     }
 }
 
-// the same on a window already in registers (w: units m0 .. m0 + 4 NW - 1 of the level)
-template <int UMAX, uint64_t MASK, bool W>
-__device__ __forceinline__ void bank_fixed_win(const float *w, const float *rt, float X[kGroup],
-                                               float best[kGroup], int bu[kGroup]) {
+// the same on a window already in registers, split in two arrays: wa holds its first 4 P4 units
+// (m0 .. m0 + 4 P4 - 1 of the level), wb the rest
+template <int UMAX, uint64_t MASK, bool W, int P4>
+__device__ __forceinline__ void bank_fixed_split(const float *wa, const float *wb, const float *rt,
+                                                 float X[kGroup], float best[kGroup], int bu[kGroup]) {
 #pragma unroll
     for (int u = 0; u < UMAX; ++u) {
 #pragma unroll
-        for (int q = 0; q < kGroup; ++q) X[q] += w[q + u];
+        for (int q = 0; q < kGroup; ++q) X[q] += (q + u < 4 * P4) ? wa[q + u] : wb[q + u - 4 * P4];
         if (((MASK >> u) & 1ull) != 0) {        // folded after unrolling
             const float r = rt[u];
 #pragma unroll
@@ -187,7 +190,7 @@ __device__ __forceinline__ void bank_fixed(const float *y, const float *rt, floa
     constexpr int NW = (kGroup + UMAX - 1 + 3) / 4;
     float w[4 * NW];
     window_load<NW>(y, w);
-    bank_fixed_win<UMAX, MASK, W>(w, rt, X, best, bu);
+    bank_fixed_split<UMAX, MASK, W, NW>(w, w, rt, X, best, bu);
 }
 
 // Any width set, with the valid-only check per slot.  Xc receives the sum over `ufull` units
@@ -465,13 +468,15 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
         uint16_t *rowW = V.W() + V.plane_off(j) + (int64_t)d * V.pitch(j);
         // a group is "fast" when the widest boxcar of its last slot ends inside the data
         const int64_t fast_lim = (int64_t)V.n_in() - base - ((int64_t)umax << k);
-        // some dense width sets: a group's window is read from LDS before the previous batch's
-        // barrier (it lies above every unit that batch writes), so its latency overlaps the
+        // the first kP4 float4 of a group's window are read from LDS before the previous batch's
+        // barrier (they lie above every unit that batch writes), so their latency overlaps the
         // previous batch's stores and barrier
-        constexpr bool kPre = StepShape<FAM, W>::PREFETCH;
-        constexpr int kWin4 = kPre ? (kGroup + Fam<FAM>::U1 - 1 + 3) / 4 : 1;
-        float win[4 * kWin4];
-        if (kPre && tid < ngroups) window_load<kWin4>(yj + tid * kGroup, win);
+        constexpr int kNW = StepShape<FAM, W>::NW;
+        constexpr int kP4 = StepShape<FAM, W>::PRE4;
+        constexpr bool kPre = kP4 > 0;
+        float win[4 * (kPre ? kP4 : 1)];
+        float win2[4 * (kNW > kP4 ? kNW - kP4 : 1)];
+        if (kPre && tid < ngroups) window_load<(kPre ? kP4 : 1)>(yj + tid * kGroup, win);
         for (int gb = 0; gb < ngroups; gb += NTH) {
             const int g = gb + tid;
             const int m0 = g * kGroup;
@@ -504,17 +509,21 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
                 for (int q = 0; q < kGroup; ++q) X[q] = has_carry ? cj[m0 + q] : 0.0f;
                 const bool fast = ((int64_t)(ma + kGroup - 1) << k) <= fast_lim;
                 if (FAM != 0 && fast && pat == 1) {
-                    if (kPre)
-                        bank_fixed_win<Fam<FAM>::U1, Fam<FAM>::M1, W>(win, rt, X, best, bu);
-                    else
+                    if constexpr (kPre) {
+                        if constexpr (kNW > kP4) window_load<kNW - kP4>(yj + m0 + 4 * kP4, win2);
+                        bank_fixed_split<Fam<FAM>::U1, Fam<FAM>::M1, W, kP4>(win, win2, rt, X, best, bu);
+                    } else {
                         bank_fixed<Fam<FAM>::U1, Fam<FAM>::M1, W>(yj + m0, rt, X, best, bu);
+                    }
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q) Xc[q] = X[q];
                 } else if (FAM != 0 && fast && pat == 2) {
-                    if (kPre)
-                        bank_fixed_win<Fam<FAM>::U2, Fam<FAM>::M2, W>(win, rt, X, best, bu);
-                    else
+                    if constexpr (kPre) {
+                        if constexpr (kNW > kP4) window_load<kNW - kP4>(yj + m0 + 4 * kP4, win2);
+                        bank_fixed_split<Fam<FAM>::U2, Fam<FAM>::M2, W, kP4>(win, win2, rt, X, best, bu);
+                    } else {
                         bank_fixed<Fam<FAM>::U2, Fam<FAM>::M2, W>(yj + m0, rt, X, best, bu);
+                    }
 #pragma unroll
                     for (int q = 0; q < kGroup; ++q) Xc[q] = X[q];
                 } else {
@@ -548,7 +557,7 @@ __device__ __forceinline__ void step_tile(const StepArgs &A, const G &V, const i
                 }
             }
             // the window of this thread's group in the next batch
-            if (kPre && g + NTH < ngroups) window_load<kWin4>(yj + (g + NTH) * kGroup, win);
+            if (kPre && g + NTH < ngroups) window_load<(kPre ? kP4 : 1)>(yj + (g + NTH) * kGroup, win);
             if (A.want_cand) {
                 const float gmax = fmaxf(fmaxf(best[0], best[1]), fmaxf(best[2], best[3]));
                 if (__ballot(gmax > A.threshold)) {
